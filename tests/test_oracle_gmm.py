@@ -1,0 +1,208 @@
+"""Pins of the oracle's Gaussian-mixture sampler (Section 5.2): the mixture
+likelihood against a brute-force allocation sum, its gradient against
+finite differences, the prior (with both change-of-variable Jacobians)
+against scipy densities and a numerical Jacobian, the sampler's invariance
+of the prior at tempering exponent 0, and the evidence of a one-component
+model against quadrature."""
+import math
+
+import numpy as np
+import pytest
+from scipy import special, stats
+
+import synth
+from closed_forms import gmm_k1_log_evidence, gmm_loglik_bruteforce
+
+
+def _phi(mu, lam, w):
+    mu, lam, w = map(np.asarray, (mu, lam, w))
+    return np.concatenate([mu, np.log(lam), np.log(w[:-1]) - np.log(w[-1])])
+
+
+@pytest.mark.parametrize("K,n", [(1, 4), (2, 5), (3, 6), (2, 1)])
+def test_loglik_bruteforce(orc, K, n):
+    rng = np.random.default_rng(K * 10 + n)
+    for _ in range(3):
+        y = rng.normal(0, 2, n)
+        mu = rng.normal(0, 2, K)
+        lam = rng.gamma(2.0, 1.0, K)
+        w = rng.dirichlet(np.ones(K))
+        ref = gmm_loglik_bruteforce(y, mu, lam, w)
+        got = orc.gmm_loglik(_phi(mu, lam, w), K, y)
+        assert got == pytest.approx(ref, abs=1e-11 * max(1, abs(ref)))
+
+
+def test_loglik_far_components_stable(orc):
+    # points far from every component: the naive sum of exps underflows, the
+    # per-point log-sum-exp does not
+    y = np.array([200.0, -150.0])
+    mu, lam, w = np.array([0.0, 1.0]), np.array([50.0, 40.0]), np.array([0.3, 0.7])
+    got = orc.gmm_loglik(_phi(mu, lam, w), 2, y)
+    ref = sum(special.logsumexp([math.log(w[j]) + stats.norm.logpdf(yk, mu[j], 1 / math.sqrt(lam[j]))
+                                 for j in range(2)]) for yk in y)
+    assert np.isfinite(got) and got == pytest.approx(ref, rel=1e-13)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 6])
+def test_loglik_gradient_finite_differences(orc, K):
+    rng = np.random.default_rng(K)
+    y = synth.gmm_data(200, np.linspace(-3, 3, max(K, 1)), 1.5, np.ones(max(K, 1)), K)
+    phi = np.concatenate([rng.normal(0, 2, K), rng.normal(0, 0.5, K), rng.normal(0, 0.5, K - 1)])
+    v, g = orc.gmm_loglik(phi, K, y, grad=True)
+    assert v == orc.gmm_loglik(phi, K, y)
+    h = 1e-6
+    for q in range(3 * K - 1):
+        e = np.zeros_like(phi)
+        e[q] = h
+        fd = (orc.gmm_loglik(phi + e, K, y) - orc.gmm_loglik(phi - e, K, y)) / (2 * h)
+        assert abs(fd - g[q]) <= 1e-6 * abs(g[q]) + 1e-4
+
+
+def _constrained_logdens(phi, K, cfg):
+    mu, eta, z = phi[:K], phi[K:2 * K], phi[2 * K:]
+    lam = np.exp(eta)
+    w = np.exp(np.append(z, 0.0) - special.logsumexp(np.append(z, 0.0)))
+    out = stats.norm.logpdf(mu, cfg.mu_mean, cfg.mu_sd).sum()
+    out += stats.gamma.logpdf(lam, a=cfg.gamma_shape, scale=1 / cfg.gamma_rate).sum()
+    if K > 1:
+        out += stats.dirichlet.logpdf(w, np.full(K, cfg.dir_rho))
+    return out
+
+
+def _map(phi, K):
+    # phi -> (mu, lambda, omega_1..omega_{K-1}), the coordinates the prior is stated in
+    mu, eta, z = phi[:K], phi[K:2 * K], phi[2 * K:]
+    w = np.exp(np.append(z, 0.0) - special.logsumexp(np.append(z, 0.0)))
+    return np.concatenate([mu, np.exp(eta), w[:-1]])
+
+
+def _log_abs_jac(phi, K):
+    D = phi.size
+    J = np.zeros((D, D))
+    h = 1e-6
+    for q in range(D):
+        e = np.zeros(D)
+        e[q] = h
+        J[:, q] = (_map(phi + e, K) - _map(phi - e, K)) / (2 * h)
+    return np.linalg.slogdet(J)[1]
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 5])
+@pytest.mark.parametrize("hyper", [(0.0, 10.0, 1.0, 1.0, 1.0), (1.0, 3.0, 2.5, 0.5, 2.0)])
+def test_logprior_matches_density_and_jacobian(orc, K, hyper):
+    m, s, a, b, rho = hyper
+    cfg = orc.gmm_cfg(1, 1, K, mu_mean=m, mu_sd=s, gamma_shape=a, gamma_rate=b, dir_rho=rho)
+    rng = np.random.default_rng(K)
+    pts = [np.concatenate([rng.normal(0, 2, K), rng.normal(0, 0.7, K), rng.normal(0, 0.7, K - 1)])
+           for _ in range(4)]
+    ref = [_constrained_logdens(p, K, cfg) + _log_abs_jac(p, K) for p in pts]
+    got = [orc.gmm_logprior(cfg, p) for p in pts]
+    for q in range(1, len(pts)):   # the prior is defined up to a constant
+        assert got[q] - got[0] == pytest.approx(ref[q] - ref[0], abs=1e-6)
+
+
+@pytest.mark.parametrize("K", [1, 3, 5])
+def test_logprior_gradient_finite_differences(orc, K):
+    cfg = orc.gmm_cfg(1, 1, K, mu_mean=0.5, mu_sd=4.0, gamma_shape=2.0, gamma_rate=0.7, dir_rho=1.5)
+    rng = np.random.default_rng(7)
+    phi = np.concatenate([rng.normal(0, 2, K), rng.normal(0, 0.5, K), rng.normal(0, 0.5, K - 1)])
+    _, g = orc.gmm_logprior(cfg, phi, grad=True)
+    h = 1e-6
+    for q in range(3 * K - 1):
+        e = np.zeros_like(phi)
+        e[q] = h
+        fd = (orc.gmm_logprior(cfg, phi + e) - orc.gmm_logprior(cfg, phi - e)) / (2 * h)
+        assert fd == pytest.approx(g[q], abs=1e-6)
+
+
+def _prior_moment_check(pop, K, n):
+    mu, eta, z = pop[:K], pop[K:2 * K], pop[2 * K:]
+    lam = np.exp(eta)
+    zz = np.vstack([z, np.zeros((1, n))])
+    w = np.exp(zz - special.logsumexp(zz, axis=0))
+    se = lambda v: math.sqrt(v / n)
+    assert np.all(np.abs(mu.mean(axis=1)) < 5 * se(100.0))
+    assert np.all(np.abs(mu.var(axis=1) - 100.0) < 5 * 100 * math.sqrt(2 / n))
+    assert np.all(np.abs(lam.mean(axis=1) - 1.0) < 5 * se(1.0))
+    assert np.all(np.abs(lam.var(axis=1) - 1.0) < 5 * math.sqrt(8.0 / n))  # var of var, Exp(1)
+    vw = (K - 1) / (K * K * (K + 1))
+    assert np.all(np.abs(w.mean(axis=1) - 1.0 / K) < 5 * se(vw))
+    assert np.all(np.abs(w.var(axis=1) - vw) < 0.1 * vw + 5 * se(vw) * 0.5)
+
+
+def rw_scales(alpha):
+    a = max(alpha, 0.02)
+    return np.array([0.15 / a, (1 + math.sqrt(1 / a)) * 0.15, (1 + math.sqrt(1 / a)) * 0.2])
+
+
+def test_init_prior_moments(orc):
+    K, n = 4, 1 << 15
+    cfg = orc.gmm_cfg(n, 11, K)
+    pop, ll, lp = orc.gmm_init(cfg, np.array([0.0, 1.0]))
+    _prior_moment_check(pop, K, n)
+
+
+def test_alpha_zero_keeps_prior(orc):
+    # with alpha == 0 all increments vanish: lw stays 0, log Z = 0, ESS = N,
+    # no resampling, and the MCMC keeps the particles distributed as the prior
+    K, n, T = 4, 1 << 14, 12
+    y = synth.gmm_data_four_components(20, 5)
+    cfg = orc.gmm_cfg(n, 21, K)
+    alpha = np.zeros(T + 1)
+    scales = np.array([rw_scales(0.0)] * (T + 1))
+    logz, hist, pop, lw = orc.gmm_run(cfg, y, alpha, scales)
+    assert logz == 0.0 and np.all(lw == 0.0)
+    assert np.allclose(hist[1:, 0], n, rtol=1e-12, atol=0) and np.all(hist[:, 1] == 0)
+    assert np.all(hist[1:, 5:8] > 0)
+    _prior_moment_check(pop, K, n)
+
+
+@pytest.mark.parametrize("move,scale", [("rw", (7.5, 1.2, 1.6)), ("mala", (2.5, 0.8, 0.8))])
+def test_point_mass_start_reaches_prior(orc, move, scale):
+    # every chain starts from the same point; under the alpha = 0 kernel the
+    # population must relax to the prior (catches kernels that never move or
+    # that leave the wrong distribution invariant)
+    K, n, sweeps = 3, 1 << 13, 80
+    y = np.array([0.3, -1.0, 2.0])
+    cfg = orc.gmm_cfg(n, 31, K, move=move)
+    start = np.concatenate([np.full(K, 3.0), np.full(K, 0.5), np.full(K - 1, -0.5)])
+    pop = np.tile(start[:, None], (1, n))
+    ll = np.full(n, orc.gmm_loglik(start, K, y))
+    lp = np.full(n, orc.gmm_logprior(cfg, start))
+    grad = None
+    if move == "mala":
+        grad = np.tile(orc.gmm_loglik(start, K, y, grad=True)[1][:, None], (1, n))
+    accepted = np.zeros(3)
+    for s in range(sweeps):
+        for b in range(3):
+            pop, ll, lp, grad, acc = orc.gmm_block(cfg, s + 1, b, 0, 0.0, scale[b], y, pop, ll, lp, grad)
+            accepted[b] += acc.mean()
+    assert np.all(accepted / sweeps > 0.05)
+    _prior_moment_check(pop, K, n)
+    # cached values stay consistent with the state
+    for i in range(0, n, n // 7):
+        assert ll[i] == pytest.approx(orc.gmm_loglik(pop[:, i], K, y), abs=1e-12)
+        assert lp[i] == pytest.approx(orc.gmm_logprior(cfg, pop[:, i]), abs=1e-12)
+        if grad is not None:
+            assert np.allclose(grad[:, i], orc.gmm_loglik(pop[:, i], K, y, grad=True)[1], atol=1e-12)
+
+
+@pytest.mark.parametrize("move", ["rw", "mala"])
+def test_k1_evidence_matches_quadrature(orc, move):
+    # one component: log p(y) by conjugacy in mu and 1-D quadrature in lambda
+    y = synth.gmm_data(30, [1.0], 2.0, [1.0], 99)
+    ref = gmm_k1_log_evidence(y, 0.0, 10.0, 1.0, 1.0)
+    T = 40
+    alpha = synth.prior_tempering(T, 4.0)
+    if move == "rw":
+        scales = np.array([rw_scales(a) for a in alpha])
+    else:
+        scales = np.array([0.5 * rw_scales(a) / 0.15 * np.array([0.15, 0.15, 0.15]) for a in alpha])
+    vals = []
+    for seed in range(1, 9):
+        cfg = orc.gmm_cfg(1 << 12, seed, 1, move=move)
+        logz, hist, _, _ = orc.gmm_run(cfg, y, alpha, scales)
+        vals.append(logz)
+    vals = np.array(vals)
+    se = vals.std(ddof=1) / math.sqrt(vals.size)
+    assert abs(vals.mean() - ref) < 4 * se + 0.02, (vals.mean(), ref, se)
