@@ -166,3 +166,19 @@ def test_weighted_mean(orc):
     W = np.exp(lw) / np.exp(lw).sum()
     est = orc.weighted_mean(x, lw)
     assert np.allclose(est, x @ W, rtol=1e-13, atol=1e-15)
+
+
+def test_ties_go_right_and_clamp(orc):
+    # equal weights: S_j = j + 1 exactly; uniforms on the boundaries
+    n = 8
+    lw = np.zeros(n)
+    u = (np.arange(n) + 1.0) / n
+    anc, S = orc.ancestors(lw, u)
+    assert np.array_equal(S, np.arange(1.0, n + 1))
+    # a_i = min{j : S_j > u_i S}: a tie moves to the next index; u = 1 has no
+    # such j and falls back to the last positive-weight particle
+    assert list(anc) == list(range(1, n)) + [n - 1]
+    lw2 = lw.copy()
+    lw2[-3:] = -np.inf          # last positive weight is index n-4
+    anc2, S2 = orc.ancestors(lw2, np.full(n, 1.0))
+    assert np.all(anc2 == n - 4)
