@@ -1,0 +1,13 @@
+"""MI355X (gfx950) sequential Monte Carlo sweep: HIP kernels behind the C ABI
+of include/smc.h, with a thin ctypes binding and drivers for the paper's two
+examples (the tracking particle filter and the tempered Gaussian-mixture
+sampler).  Importing the package loads libsmc.so and fails if it is absent.
+"""
+from . import _lib
+from ._lib import SmcError
+
+_lib.load()
+
+from .sampler import ParticleFilter  # noqa: E402
+
+__all__ = ["ParticleFilter", "SmcError"]

@@ -1,0 +1,256 @@
+"""ctypes binding of libsmc.so (declarations in include/smc.h).
+
+Argument marshalling only: every step of the sweep runs in the HIP kernels
+of the library.  Function names match the C entry points.  Loading fails
+loudly when the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmc.so")
+
+SMC_ABI_VERSION = 1
+
+# smc_status
+SMC_OK, SMC_ERR_INVALID_ARG, SMC_ERR_BAD_STATE, SMC_ERR_DEVICE, SMC_ERR_NUMERIC, \
+    SMC_ERR_UNSUPPORTED = range(6)
+# smc_model, smc_scheme, smc_precision, smc_move_kind
+SMC_MODEL_CV_TRACK, SMC_MODEL_GMM_TEMPERED = 1, 2
+SMC_RS_MULTINOMIAL, SMC_RS_SYSTEMATIC, SMC_RS_STRATIFIED = 0, 1, 2
+SMC_F64, SMC_F32_STATE = 0, 1
+SMC_MOVE_RW, SMC_MOVE_MALA = 0, 1
+SCHEMES = {"multinomial": SMC_RS_MULTINOMIAL, "systematic": SMC_RS_SYSTEMATIC,
+           "stratified": SMC_RS_STRATIFIED}
+
+# scalar block and history layout
+(SMC_S_L, SMC_S_L2, SMC_S_LOGZ, SMC_S_ESS, SMC_S_DLOGZ, SMC_S_FLAG, SMC_S_M, SMC_S_STOT,
+ SMC_S_RESAMPLED, SMC_S_U, SMC_S_LPRE) = range(11)
+SMC_SCALARS_LEN = 16
+(SMC_H_ESS, SMC_H_FLAG, SMC_H_DLOGZ, SMC_H_LOGZ, SMC_H_L, SMC_H_ACC0, SMC_H_ACC1, SMC_H_ACC2,
+ SMC_H_PATH, SMC_H_MON) = range(10)
+SMC_HIST_COLS = 16
+SMC_DEVERR_ZERO_WEIGHTS, SMC_DEVERR_NONFINITE, SMC_DEVERR_GAMMA = 1, 2, 4
+
+_i32, _i64, _u32, _u64, _d, _vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                   ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p)
+
+
+class smc_config(ctypes.Structure):
+    _fields_ = [("abi_version", _i32), ("model", _i32), ("precision", _i32), ("scheme", _i32),
+                ("n", _i64), ("threshold", _d), ("seed", _u64), ("problem_id", _u32),
+                ("paper_compatible_loglik", _i32),
+                ("dt", _d), ("sd_pos", _d), ("sd_vel", _d), ("obs_scale", _d), ("obs_nu", _d),
+                ("init_sd", _d * 4), ("n_obs", _i32),
+                ("K", _i32), ("n_data", _i64), ("prior_mu_mean", _d), ("prior_mu_sd", _d),
+                ("prior_gamma_shape", _d), ("prior_gamma_rate", _d), ("prior_dir_rho", _d),
+                ("move_kind", _i32), ("sweeps", _i32)]
+
+
+class smc_buffers(ctypes.Structure):
+    _fields_ = [("state", _vp), ("state_alt", _vp), ("log_weight", _vp), ("ancestors", _vp),
+                ("data", _vp), ("history", _vp), ("history_len", _i64), ("workspace", _vp),
+                ("workspace_bytes", ctypes.c_size_t), ("scalars", _vp)]
+
+
+class smc_move_args(ctypes.Structure):
+    _fields_ = [("obs_index", _i32), ("fuse_reweight", _i32), ("alpha", _d), ("scale", _d * 3),
+                ("sweeps", _i32)]
+
+
+class smc_reweight_args(ctypes.Structure):
+    _fields_ = [("obs_index", _i32), ("dalpha", _d)]
+
+
+class SmcError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        super().__init__("%s failed: status %d (%s)%s" % (
+            where, status, STATUS_NAMES.get(status, "?"), (": " + detail) if detail else ""))
+
+
+STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "call out of order", 3: "device error",
+                4: "numeric failure on the device", 5: "unsupported"}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libsmc.so; raises if it has not been built (no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsmc.so is not built (%s); run __graft_entry__.build() or "
+                          "python paper_1306_5583_amd/build.py" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    st = _i32
+    P = ctypes.POINTER
+    sigs = {
+        "smc_status_string": (ctypes.c_char_p, [st]),
+        "smc_state_rows": (st, [P(smc_config), P(_i32), P(_i32)]),
+        "smc_workspace_size": (st, [P(smc_config), P(ctypes.c_size_t)]),
+        "smc_create": (st, [P(smc_config), P(smc_buffers), _vp, P(_vp)]),
+        "smc_destroy": (st, [_vp]),
+        "smc_set_stream": (st, [_vp, _vp]),
+        "smc_init": (st, [_vp]),
+        "smc_move": (st, [_vp, _i32, P(smc_move_args)]),
+        "smc_reweight": (st, [_vp, _i32, P(smc_reweight_args)]),
+        "smc_ess": (st, [_vp, _i32, P(_d)]),
+        "smc_resample": (st, [_vp, _i32, _i32]),
+        "smc_monitor": (st, [_vp, _i32, _vp]),
+        "smc_gather": (st, [_vp]),
+        "smc_current_state": (st, [_vp, P(_vp)]),
+        "smc_read_scalars": (st, [_vp, P(_d)]),
+        "smc_check": (st, [_vp]),
+        "smc_last_error": (ctypes.c_char_p, [_vp]),
+        "smc_gmm_loglik_grad": (st, [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp, _vp, _vp]),
+        "smc_draw_words": (st, [_u64, _u32, _u32, _u32, _u32, _i64, _vp, _vp]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return ["smc_status_string", "smc_state_rows", "smc_workspace_size", "smc_create",
+            "smc_destroy", "smc_set_stream", "smc_init", "smc_move", "smc_reweight", "smc_ess",
+            "smc_resample", "smc_monitor", "smc_gather", "smc_current_state",
+            "smc_read_scalars", "smc_check", "smc_last_error", "smc_gmm_loglik_grad",
+            "smc_draw_words"]
+
+
+def _check(status, where, ctx=None):
+    if status != SMC_OK:
+        detail = ""
+        if ctx is not None:
+            msg = load().smc_last_error(ctx)
+            detail = msg.decode() if msg else ""
+        raise SmcError(status, where, detail)
+
+
+# --------------------------------------------------------------- wrappers ---
+
+def make_config(model, n, *, seed=1, problem_id=0, scheme="systematic", threshold=0.5,
+                precision=SMC_F64, paper_compatible=False, dt=0.1, sd_pos=0.02, sd_vel=0.5,
+                obs_scale=0.1, obs_nu=10.0, init_sd=(1.0, 1.0, 1.0, 1.0), n_obs=1, K=1,
+                n_data=1, prior=(0.0, 10.0, 1.0, 1.0, 1.0), move_kind=SMC_MOVE_RW, sweeps=1):
+    c = smc_config()
+    c.abi_version = SMC_ABI_VERSION
+    c.model = model
+    c.precision = precision
+    c.scheme = SCHEMES.get(scheme, scheme)
+    c.n = n
+    c.threshold = threshold
+    c.seed = seed
+    c.problem_id = problem_id
+    c.paper_compatible_loglik = int(paper_compatible)
+    c.dt, c.sd_pos, c.sd_vel, c.obs_scale, c.obs_nu = dt, sd_pos, sd_vel, obs_scale, obs_nu
+    for k in range(4):
+        c.init_sd[k] = init_sd[k]
+    c.n_obs = n_obs
+    c.K = K
+    c.n_data = n_data
+    (c.prior_mu_mean, c.prior_mu_sd, c.prior_gamma_shape, c.prior_gamma_rate,
+     c.prior_dir_rho) = prior
+    c.move_kind = move_kind
+    c.sweeps = sweeps
+    return c
+
+
+def smc_state_rows(cfg):
+    rows, eb = _i32(), _i32()
+    _check(load().smc_state_rows(ctypes.byref(cfg), ctypes.byref(rows), ctypes.byref(eb)),
+           "smc_state_rows")
+    return rows.value, eb.value
+
+
+def smc_workspace_size(cfg):
+    b = ctypes.c_size_t()
+    _check(load().smc_workspace_size(ctypes.byref(cfg), ctypes.byref(b)), "smc_workspace_size")
+    return b.value
+
+
+def smc_create(cfg, bufs, stream_handle):
+    ctx = _vp()
+    _check(load().smc_create(ctypes.byref(cfg), ctypes.byref(bufs), _vp(stream_handle),
+                             ctypes.byref(ctx)), "smc_create")
+    return ctx
+
+
+def smc_destroy(ctx):
+    _check(load().smc_destroy(ctx), "smc_destroy")
+
+
+def smc_set_stream(ctx, stream_handle):
+    _check(load().smc_set_stream(ctx, _vp(stream_handle)), "smc_set_stream", ctx)
+
+
+def smc_init(ctx):
+    _check(load().smc_init(ctx), "smc_init", ctx)
+
+
+def smc_move(ctx, step, args):
+    _check(load().smc_move(ctx, step, ctypes.byref(args)), "smc_move", ctx)
+
+
+def smc_reweight(ctx, step, args):
+    _check(load().smc_reweight(ctx, step, ctypes.byref(args)), "smc_reweight", ctx)
+
+
+def smc_ess(ctx, step, host=False):
+    if host:
+        v = _d()
+        _check(load().smc_ess(ctx, step, ctypes.byref(v)), "smc_ess", ctx)
+        return v.value
+    _check(load().smc_ess(ctx, step, None), "smc_ess", ctx)
+    return None
+
+
+def smc_resample(ctx, step, force=False):
+    _check(load().smc_resample(ctx, step, int(force)), "smc_resample", ctx)
+
+
+def smc_monitor(ctx, step, out_ptr=None):
+    _check(load().smc_monitor(ctx, step, _vp(out_ptr) if out_ptr else None), "smc_monitor", ctx)
+
+
+def smc_gather(ctx):
+    _check(load().smc_gather(ctx), "smc_gather", ctx)
+
+
+def smc_current_state(ctx):
+    p = _vp()
+    _check(load().smc_current_state(ctx, ctypes.byref(p)), "smc_current_state", ctx)
+    return p.value
+
+
+def smc_read_scalars(ctx):
+    out = (_d * SMC_SCALARS_LEN)()
+    _check(load().smc_read_scalars(ctx, out), "smc_read_scalars", ctx)
+    return list(out)
+
+
+def smc_check(ctx):
+    _check(load().smc_check(ctx), "smc_check", ctx)
+
+
+def smc_gmm_loglik_grad(mu_ptr, eta_ptr, z_ptr, n, K, y_ptr, n_data, ll_ptr, grad_ptr,
+                        stream_handle):
+    _check(load().smc_gmm_loglik_grad(_vp(mu_ptr), _vp(eta_ptr), _vp(z_ptr), n, K, _vp(y_ptr),
+                                      n_data, _vp(ll_ptr), _vp(grad_ptr) if grad_ptr else None,
+                                      _vp(stream_handle)), "smc_gmm_loglik_grad")
+
+
+def smc_draw_words(seed, step, tag, call, problem, n, out_ptr, stream_handle):
+    _check(load().smc_draw_words(seed, step, tag, call, problem, n, _vp(out_ptr),
+                                 _vp(stream_handle)), "smc_draw_words")
+
+
+INF = math.inf

@@ -1,0 +1,301 @@
+// smc_device.hpp -- device building blocks of the SMC sweep for gfx950:
+// Philox4x32-10 counter-based draws and their transforms, and deterministic
+// (fixed-order) wavefront/workgroup reductions and scans.
+//
+// Tiling used by every per-particle kernel: a workgroup of TPB = 256 lanes
+// (four wave64s) owns a tile of TILE = 1024 consecutive particles; lane t
+// handles particles tile_base + k*256 + t for k = 0..3, so every load and
+// store of a structure-of-arrays row is a fully coalesced 256-lane access.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smc {
+
+constexpr int WAVE = 64;
+constexpr int TPB = 256;
+constexpr int ITEMS = 4;
+constexpr int TILE = TPB * ITEMS;
+constexpr int NWAVES = TPB / WAVE;
+
+// Counter tags: counter = (particle, step, tag << 16 | call, problem).
+enum : uint32_t {
+    TAG_INIT = 1,
+    TAG_PF_MOVE = 2,
+    TAG_MH_MU = 3,
+    TAG_MH_ETA = 4,
+    TAG_MH_Z = 5,
+    TAG_MH_ACCEPT = 6,
+    TAG_RESAMPLE = 7
+};
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr float kTwoPiF = 6.28318530717958647692f;
+
+struct Key {
+    uint32_t k0, k1;
+};
+
+__host__ __device__ inline Key make_key(uint64_t seed)
+{
+    return Key{(uint32_t)seed, (uint32_t)(seed >> 32)};
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// multiplies, the Weyl key schedule between rounds.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        Key key)
+{
+    uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint4 draw(Key key, uint32_t i, uint32_t t, uint32_t tag, uint32_t j,
+                                      uint32_t p)
+{
+    return philox(i, t, (tag << 16) | (j & 0xFFFFu), p, key);
+}
+
+// Uniform on (0,1]: (top 53 bits of (a:b) + 1) * 2^-53, assembled exactly.
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b)
+{
+    return fma((double)a, 0x1p-32, (double)((b >> 11) + 1u) * 0x1p-53);
+}
+
+// Uniform on (0,1] in single precision: ((w >> 8) + 1) * 2^-24.
+__device__ __forceinline__ float u24(uint32_t w)
+{
+    return (float)((w >> 8) + 1u) * 0x1p-24f;
+}
+
+// Box-Muller: two standard normals from the four words of one call.
+__device__ __forceinline__ double2 normal2(uint4 w)
+{
+    const double u1 = u53(w.x, w.y);
+    const double u2 = u53(w.z, w.w);
+    const double r = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincos(kTwoPi * u2, &s, &c);
+    return make_double2(r * c, r * s);
+}
+
+// Single-precision Box-Muller: four normals from one call.
+__device__ __forceinline__ float4 normal4f(uint4 w)
+{
+    float s0, c0, s1, c1;
+    const float r0 = sqrtf(-2.0f * logf(u24(w.x)));
+    sincosf(kTwoPiF * u24(w.y), &s0, &c0);
+    const float r1 = sqrtf(-2.0f * logf(u24(w.z)));
+    sincosf(kTwoPiF * u24(w.w), &s1, &c1);
+    return make_float4(r0 * c0, r0 * s0, r1 * c1, r1 * s1);
+}
+
+// Gamma(shape, 1) from calls jbase, jbase+1, ...: exponential for shape 1,
+// Marsaglia-Tsang with attempt k on calls jbase+1+2k (normal) and jbase+2+2k
+// (uniform), boosted by u^(1/shape) (call jbase) for shape < 1.  *fail is set
+// after 31 rejected attempts.
+__device__ inline double gamma_draw(Key key, uint32_t i, uint32_t t, uint32_t tag,
+                                    uint32_t jbase, uint32_t p, double shape, int *fail)
+{
+    if (shape == 1.0) {
+        const uint4 w = draw(key, i, t, tag, jbase, p);
+        return -log(u53(w.x, w.y));
+    }
+    const double a = shape < 1.0 ? shape + 1.0 : shape;
+    const double d = a - 1.0 / 3.0;
+    const double c = 1.0 / sqrt(9.0 * d);
+    double g = __builtin_nan("");
+    for (int k = 0; k < 31; ++k) {
+        const double z = normal2(draw(key, i, t, tag, jbase + 1 + 2 * k, p)).x;
+        double v = 1.0 + c * z;
+        if (v <= 0.0)
+            continue;
+        v = v * v * v;
+        const uint4 w = draw(key, i, t, tag, jbase + 2 + 2 * k, p);
+        const double u = u53(w.x, w.y);
+        if (log(u) < 0.5 * z * z + d - d * v + d * log(v)) {
+            g = d * v;
+            break;
+        }
+    }
+    if (g != g) {
+        *fail = 1;
+        return g;
+    }
+    if (shape < 1.0) {
+        const uint4 w = draw(key, i, t, tag, jbase, p);
+        g *= pow(u53(w.x, w.y), 1.0 / shape);
+    }
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions.  Butterfly (xor) exchanges leave every lane of a
+// wave with the same value; workgroup results combine the per-wave values in
+// wave order.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / WAVE; }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = WAVE / 2; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = WAVE / 2; off >= 1; off >>= 1)
+        v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int off = WAVE / 2; off >= 1; off >>= 1)
+        v = fmin(v, __shfl_xor(v, off));
+    return v;
+}
+
+// Block reductions over NW waves; `red` is __shared__ scratch of >= NW
+// doubles.  All threads receive the result.
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane_id() == 0)
+        red[wave_id()] = v;
+    __syncthreads();
+    double s = red[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+        s += red[w];
+    return s;
+}
+
+template <int NW>
+__device__ __forceinline__ double block_max(double v, double *red)
+{
+    v = wave_max(v);
+    __syncthreads();
+    if (lane_id() == 0)
+        red[wave_id()] = v;
+    __syncthreads();
+    double s = red[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+        s = fmax(s, red[w]);
+    return s;
+}
+
+// Inclusive prefix sum across one wave (Hillis-Steele).
+__device__ __forceinline__ double wave_incl_scan(double v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const double o = __shfl_up(v, d);
+        if (lane >= d)
+            v += o;
+    }
+    return v;
+}
+
+// Inclusive prefix sum across the workgroup; *total receives the sum.
+template <int NW>
+__device__ __forceinline__ double block_incl_scan(double v, double *red, double *total)
+{
+    v = wave_incl_scan(v);
+    __syncthreads();
+    if (lane_id() == WAVE - 1)
+        red[wave_id()] = v;
+    __syncthreads();
+    double before = 0.0, all = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (w < wave_id())
+            before += red[w];
+        all += red[w];
+    }
+    *total = all;
+    return before + v;
+}
+
+// Inclusive prefix max across the workgroup (exact, order-free).
+template <int NW>
+__device__ __forceinline__ double block_incl_max_scan(double v, double *red)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const double o = __shfl_up(v, d);
+        if (lane >= d)
+            v = fmax(v, o);
+    }
+    __syncthreads();
+    if (lane == WAVE - 1)
+        red[wave_id()] = v;
+    __syncthreads();
+    for (int w = 0; w < wave_id(); ++w)
+        v = fmax(v, red[w]);
+    return v;
+}
+
+// Per-tile weight summary written by every kernel that changes log-weights:
+// m = max lw over the tile, s1 = sum exp(lw - m), s2 = sum exp(2 (lw - m)).
+struct TilePartial {
+    double m, s1, s2, pad;
+};
+
+// Reduces the ITEMS log-weights held by each lane of a TPB workgroup to a
+// TilePartial (written by lane 0).  Out-of-range items must be -inf.
+__device__ __forceinline__ void tile_partial(const double (&lw)[ITEMS], TilePartial *out,
+                                             double *red)
+{
+    double m = lw[0];
+#pragma unroll
+    for (int k = 1; k < ITEMS; ++k)
+        m = fmax(m, lw[k]);
+    m = block_max<NWAVES>(m, red);
+    double s1 = 0.0, s2 = 0.0;
+    if (m > -INFINITY) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const double e = lw[k] > -INFINITY ? exp(lw[k] - m) : 0.0;
+            s1 += e;
+            s2 += e * e;
+        }
+    }
+    s1 = block_sum<NWAVES>(s1, red);
+    s2 = block_sum<NWAVES>(s2, red);
+    if (threadIdx.x == 0) {
+        out->m = m;
+        out->s1 = s1;
+        out->s2 = s2;
+        out->pad = 0.0;
+    }
+}
+
+}  // namespace smc

@@ -1,0 +1,133 @@
+"""Drivers that own torch device buffers and call the C ABI in the order of
+the paper's algorithms.  Host logic only: every numeric step is a HIP kernel
+behind include/smc.h.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+class _Base:
+    """Common buffer set: state ping-pong pair, log-weights, ancestors,
+    data, history, workspace and the scalar block."""
+
+    def __init__(self, cfg, data: torch.Tensor, history_len: int, device, stream):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        rows, eb = L.smc_state_rows(cfg)
+        dt = torch.float32 if eb == 4 else torch.float64
+        n = int(cfg.n)
+        self.n = n
+        self.rows = rows
+        self.state_a = torch.zeros((rows, n), dtype=dt, device=self.device)
+        self.state_b = torch.zeros((rows, n), dtype=dt, device=self.device)
+        self.log_weight = torch.zeros(n, dtype=torch.float64, device=self.device)
+        self.ancestors = torch.zeros(n, dtype=torch.int32, device=self.device)
+        self.data = data.to(self.device, torch.float64).contiguous()
+        self.history = torch.zeros((max(history_len, 1), L.SMC_HIST_COLS), dtype=torch.float64,
+                                   device=self.device)
+        ws = L.smc_workspace_size(cfg)
+        self.workspace = torch.zeros(ws + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws_ptr = self.workspace.data_ptr() + off
+        self.ws_bytes = ws
+        self.scalars = torch.zeros(L.SMC_SCALARS_LEN, dtype=torch.float64, device=self.device)
+        b = L.smc_buffers()
+        b.state = self.state_a.data_ptr()
+        b.state_alt = self.state_b.data_ptr()
+        b.log_weight = self.log_weight.data_ptr()
+        b.ancestors = self.ancestors.data_ptr()
+        b.data = self.data.data_ptr()
+        b.history = self.history.data_ptr()
+        b.history_len = history_len
+        b.workspace = self.ws_ptr
+        b.workspace_bytes = ws
+        b.scalars = self.scalars.data_ptr()
+        self._bufs = b
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = L.smc_create(cfg, b, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.smc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def state(self) -> torch.Tensor:
+        """The buffer currently holding the state ([rows][n])."""
+        p = L.smc_current_state(self.ctx)
+        return self.state_a if p == self.state_a.data_ptr() else self.state_b
+
+    def scalars_host(self):
+        return L.smc_read_scalars(self.ctx)
+
+    def log_z(self) -> float:
+        return self.scalars_host()[L.SMC_S_LOGZ]
+
+    def check(self):
+        L.smc_check(self.ctx)
+
+
+class ParticleFilter(_Base):
+    """Bootstrap filter of the almost-constant-velocity model (Section 5.1,
+    Algorithm 'pf') over observations y[T][2]."""
+
+    def __init__(self, n: int, y, *, seed: int = 1, scheme: str = "systematic",
+                 threshold: float = 0.5, fp32_state: bool = False, obs_nu: float = 10.0,
+                 obs_scale: float = 0.1, dt: float = 0.1, sd_pos: float = 0.02,
+                 sd_vel: float = 0.5, init_sd=(1.0, 1.0, 1.0, 1.0), paper_compatible=False,
+                 problem_id: int = 0, device="cuda", stream=None):
+        y = torch.as_tensor(np.ascontiguousarray(y, dtype=np.float64))
+        T = int(y.shape[0])
+        cfg = L.make_config(L.SMC_MODEL_CV_TRACK, n, seed=seed, problem_id=problem_id,
+                            scheme=scheme, threshold=threshold,
+                            precision=L.SMC_F32_STATE if fp32_state else L.SMC_F64,
+                            paper_compatible=paper_compatible, dt=dt, sd_pos=sd_pos,
+                            sd_vel=sd_vel, obs_scale=obs_scale, obs_nu=obs_nu, init_sd=init_sd,
+                            n_obs=T)
+        self.T = T
+        super().__init__(cfg, y, T, device, stream)
+        self._margs = L.smc_move_args()
+        self._margs.fuse_reweight = 1
+
+    def init(self, monitor: bool = True):
+        L.smc_init(self.ctx)
+        L.smc_ess(self.ctx, 0)
+        L.smc_resample(self.ctx, 0)
+        if monitor:
+            L.smc_monitor(self.ctx, 0)
+
+    def step(self, t: int, monitor: bool = True):
+        """One iteration: move + weight (fused), normalise, resample if
+        ESS < threshold N, monitor."""
+        self._margs.obs_index = t
+        L.smc_move(self.ctx, t, self._margs)
+        L.smc_ess(self.ctx, t)
+        L.smc_resample(self.ctx, t)
+        if monitor:
+            L.smc_monitor(self.ctx, t)
+
+    def run(self, monitor: bool = True) -> float:
+        self.init(monitor)
+        for t in range(1, self.T):
+            self.step(t, monitor)
+        return self.log_z()
+
+    def history_host(self) -> np.ndarray:
+        torch.cuda.synchronize(self.device)
+        return self.history.cpu().numpy()

@@ -1,0 +1,123 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every entry point include/smc.h declares, and argument validation
+answers with status codes before any device work."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1306_5583_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "smc.h")).read()
+    return sorted(set(re.findall(r"^(?:smc_status|const char \*)\s*(smc_\w+)\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 18
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(L.exported_symbols())
+
+
+def test_status_strings(L):
+    lib = L.load()
+    assert lib.smc_status_string(0) == b"ok"
+    assert lib.smc_status_string(4).startswith(b"numeric")
+
+
+def test_config_validation(L):
+    c = L.make_config(L.SMC_MODEL_CV_TRACK, 1000, n_obs=10)
+    assert L.smc_state_rows(c) == (4, 8)
+    c32 = L.make_config(L.SMC_MODEL_CV_TRACK, 1000, n_obs=10, precision=L.SMC_F32_STATE)
+    assert L.smc_state_rows(c32) == (4, 4)
+    g = L.make_config(L.SMC_MODEL_GMM_TEMPERED, 1000, K=4, n_data=10)
+    assert L.smc_state_rows(g) == (3 * 4 - 1 + 2, 8)
+    gm = L.make_config(L.SMC_MODEL_GMM_TEMPERED, 1000, K=4, n_data=10, move_kind=L.SMC_MOVE_MALA)
+    assert L.smc_state_rows(gm) == (2 * 11 + 2, 8)
+    assert L.smc_workspace_size(c) > 0
+    bad = [
+        L.make_config(L.SMC_MODEL_CV_TRACK, 0, n_obs=10),
+        L.make_config(L.SMC_MODEL_CV_TRACK, 2 ** 31, n_obs=10),
+        L.make_config(L.SMC_MODEL_CV_TRACK, 10, n_obs=0),
+        L.make_config(L.SMC_MODEL_CV_TRACK, 10, n_obs=3, threshold=math.nan),
+        L.make_config(L.SMC_MODEL_CV_TRACK, 10, n_obs=3, obs_scale=0.0),
+        L.make_config(L.SMC_MODEL_CV_TRACK, 10, n_obs=3, scheme=7),
+        L.make_config(L.SMC_MODEL_GMM_TEMPERED, 10, K=0, n_data=5),
+        L.make_config(L.SMC_MODEL_GMM_TEMPERED, 10, K=17, n_data=5),
+        L.make_config(L.SMC_MODEL_GMM_TEMPERED, 10, K=2, n_data=0),
+        L.make_config(L.SMC_MODEL_GMM_TEMPERED, 10, K=2, n_data=5, prior=(0, -1, 1, 1, 1)),
+        L.make_config(3, 10),
+    ]
+    for b in bad:
+        with pytest.raises(L.SmcError) as e:
+            L.smc_workspace_size(b)
+        assert e.value.status == L.SMC_ERR_INVALID_ARG
+    v = L.make_config(L.SMC_MODEL_CV_TRACK, 10, n_obs=3)
+    v.abi_version = 99
+    with pytest.raises(L.SmcError):
+        L.smc_state_rows(v)
+
+
+def test_multinomial_needs_more_workspace(L):
+    a = L.smc_workspace_size(L.make_config(L.SMC_MODEL_CV_TRACK, 1 << 20, n_obs=3))
+    b = L.smc_workspace_size(L.make_config(L.SMC_MODEL_CV_TRACK, 1 << 20, n_obs=3,
+                                           scheme="multinomial"))
+    assert b >= a + 8 * ((1 << 20) + 1)
+
+
+def _fake_buffers(L, ws):
+    b = L.smc_buffers()
+    b.state, b.state_alt, b.log_weight, b.ancestors = 0x10000, 0x20000, 0x30000, 0x40000
+    b.data, b.history, b.history_len = 0x50000, 0x60000, 4
+    b.workspace, b.workspace_bytes, b.scalars = 0x70000, ws, 0x80000
+    return b
+
+
+def test_buffer_validation_before_device(L):
+    c = L.make_config(L.SMC_MODEL_CV_TRACK, 1000, n_obs=3)
+    ws = L.smc_workspace_size(c)
+    b = _fake_buffers(L, ws - 1)
+    with pytest.raises(L.SmcError) as e:
+        L.smc_create(c, b, None)
+    assert e.value.status == L.SMC_ERR_INVALID_ARG        # workspace too small
+    b = _fake_buffers(L, ws)
+    b.workspace = 0x70008
+    with pytest.raises(L.SmcError) as e:
+        L.smc_create(c, b, None)
+    assert e.value.status == L.SMC_ERR_INVALID_ARG        # misaligned
+    b = _fake_buffers(L, ws)
+    b.state_alt = b.state
+    with pytest.raises(L.SmcError) as e:
+        L.smc_create(c, b, None)
+    assert e.value.status == L.SMC_ERR_INVALID_ARG        # aliasing ping-pong pair
+
+
+def test_create_without_device_reports_device_error(L):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    c = L.make_config(L.SMC_MODEL_CV_TRACK, 1000, n_obs=3)
+    b = _fake_buffers(L, L.smc_workspace_size(c))
+    with pytest.raises(L.SmcError) as e:
+        L.smc_create(c, b, None)
+    assert e.value.status == L.SMC_ERR_DEVICE
+
+
+def test_null_context_rejected(L):
+    lib = L.load()
+    assert lib.smc_init(None) == L.SMC_ERR_INVALID_ARG
+    assert lib.smc_resample(None, 0, 0) == L.SMC_ERR_INVALID_ARG
+    assert lib.smc_check(None) == L.SMC_ERR_INVALID_ARG
