@@ -76,14 +76,16 @@ def run_pf(args, n, fp32, scheme, steps, warmup, timing=True):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record(stream)
+        # fused move + weight; the same pass completes the previous step's monitor
         m.obs_index = t
+        m.monitor_step = t - 1
         L.smc_move(pf.ctx, t, m)
         if timing:
             b.record(stream)
             ev.append((a, b))
         L.smc_ess(pf.ctx, t)
         L.smc_resample(pf.ctx, t)
-        L.smc_monitor(pf.ctx, t)
+    L.smc_monitor(pf.ctx, warmup + steps)   # the last step's monitor
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     pf.check()

@@ -165,6 +165,14 @@ typedef struct smc_move_args {
     double alpha;          /* GMM: tempering exponent of the MCMC target */
     double scale[3];       /* GMM: per-block random-walk sd or MALA step (mu, eta, z) */
     int32_t sweeps;        /* GMM: passes over the blocks; 0 = config value */
+    /* CV with fuse_reweight: when >= 0, the same pass also accumulates the
+     * importance-sampling estimate of the INCOMING population (the monitor
+     * of step monitor_step, exactly what smc_monitor(ctx, monitor_step, ...)
+     * would compute after that step's resample); the following smc_ess
+     * completes it into history row monitor_step and, when non-NULL,
+     * monitor_out[4] (device).  -1 = off. */
+    int32_t monitor_step;
+    double *monitor_out;
 } smc_move_args;
 
 typedef struct smc_reweight_args {

@@ -58,7 +58,12 @@ class smc_buffers(ctypes.Structure):
 
 class smc_move_args(ctypes.Structure):
     _fields_ = [("obs_index", _i32), ("fuse_reweight", _i32), ("alpha", _d), ("scale", _d * 3),
-                ("sweeps", _i32)]
+                ("sweeps", _i32), ("monitor_step", _i32), ("monitor_out", _vp)]
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        if "monitor_step" not in k:
+            self.monitor_step = -1
 
 
 class smc_reweight_args(ctypes.Structure):

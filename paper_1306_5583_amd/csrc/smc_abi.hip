@@ -337,7 +337,16 @@ smc_status smc_move(smc_ctx *ctx, int32_t step, const smc_move_args *args)
         if (args->obs_index < 0 || args->obs_index >= c.cfg.n_obs)
             return fail(c, SMC_ERR_INVALID_ARG, "obs_index out of range");
         const bool fuse = args->fuse_reweight != 0;
-        e = launch_pf_move(c, step, args->obs_index, fuse, c.armed_gather, fuse && c.armed_lw);
+        const bool mon = fuse && args->monitor_step >= 0;
+        if (mon && !c.normalised)
+            return fail(c, SMC_ERR_BAD_STATE, "a fused monitor needs normalised incoming weights");
+        e = launch_pf_move(c, step, args->obs_index, fuse, c.armed_gather, fuse && c.armed_lw,
+                           mon);
+        if (mon) {
+            c.mon_pending_step = args->monitor_step;
+            c.mon_pending_rows = 4;
+            c.mon_pending_out = args->monitor_out;
+        }
         c.armed_gather = false;
         if (fuse) {
             c.armed_lw = false;

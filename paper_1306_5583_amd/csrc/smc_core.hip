@@ -8,8 +8,6 @@
 
 namespace smc {
 
-constexpr int FIN_TPB = 1024;
-constexpr int FIN_NW = FIN_TPB / WAVE;
 
 // ---------------------------------------------------------------------------
 // Scalar block reset (initialisation): L = log N, log Z = 0.
@@ -38,93 +36,144 @@ hipError_t launch_reset_scalars(Ctx &c)
 
 // ---------------------------------------------------------------------------
 // Cumulative offsets of `count` non-negative tile values v_b (computed by
-// `val(b)`) in one workgroup: out[b] = sum_{b' < b} v_b', out[count] = total.
-// Fixed-order (chunked sequential + workgroup scan) and forced monotone by
-// an exact running maximum, so that equal inputs always give equal outputs
-// and out[] never decreases.
+// `val(b)`) in one workgroup of FIN_PASS_TPB lanes: out[b] = sum_{b' < b} v_b',
+// out[count] = total.  Values are staged through LDS in passes of FIN_PASS;
+// each lane sums a contiguous chunk of FIN_CH values sequentially, the
+// chunk totals are scanned across the workgroup in a fixed order, and an
+// exact running maximum keeps out[] non-decreasing.  The same inputs always
+// give the same outputs.
 // ---------------------------------------------------------------------------
-template <int NW, typename F>
-__device__ double tile_offsets(int64_t count, F val, double *out, double *red)
+constexpr int FIN_CH = 16;
+constexpr int FIN_PASS_TPB = 256;
+constexpr int FIN_PASS = FIN_PASS_TPB * FIN_CH;
+constexpr int FIN_LDS = FIN_PASS_TPB * (FIN_CH + 1);  // padded chunks: no bank conflicts
+
+__device__ __forceinline__ int fin_pidx(int j) { return (j / FIN_CH) * (FIN_CH + 1) + j % FIN_CH; }
+
+template <typename F>
+__device__ double tile_offsets(int64_t count, F val, double *out, double *sv, double *red)
 {
+    constexpr int NW = FIN_PASS_TPB / WAVE;
     const int tid = threadIdx.x;
-    const int nthr = NW * WAVE;
-    const int64_t chunk = ceil_div(count, nthr);
-    const int64_t b0 = min((int64_t)tid * chunk, count);
-    const int64_t b1 = min(b0 + chunk, count);
-    double loc = 0.0;
-    for (int64_t b = b0; b < b1; ++b)
-        loc += val(b);
-    double total;
-    const double incl = block_incl_scan<NW>(loc, red, &total);
-    // exclusive prefix = the inclusive value of the previous lane
-    double excl = __shfl_up(incl, 1);
-    __syncthreads();
-    if (lane_id() == WAVE - 1)
-        red[wave_id()] = incl;
-    __syncthreads();
-    if (lane_id() == 0)
-        excl = wave_id() == 0 ? 0.0 : red[wave_id() - 1];
-    // running values inside the chunk, clamped below by all earlier chunks
-    double run = excl, last = excl;
-    for (int64_t b = b0; b < b1; ++b) {
-        last = run;
-        run += val(b);
+    double carry = 0.0;
+    for (int64_t pbase = 0; pbase < count; pbase += FIN_PASS) {
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < FIN_CH; ++k) {
+            const int j = k * FIN_PASS_TPB + tid;
+            const int64_t b = pbase + j;
+            sv[fin_pidx(j)] = b < count ? val(b) : 0.0;
+        }
+        __syncthreads();
+        double e[FIN_CH];
+        double run = 0.0;
+#pragma unroll
+        for (int j = 0; j < FIN_CH; ++j) {
+            e[j] = run;
+            run += sv[tid * (FIN_CH + 1) + j];
+        }
+        double total;
+        const double excl = block_excl_scan<NW>(run, red, &total);
+        // candidate offsets, then the exact floor from all earlier chunks
+        double last = 0.0;
+#pragma unroll
+        for (int j = 0; j < FIN_CH; ++j) {
+            e[j] = carry + (excl + e[j]);
+            last = fmax(last, e[j]);
+        }
+        const double incl_max = block_incl_max_scan<NW>(last, red);
+        double floor_v = __shfl_up(incl_max, 1);
+        __syncthreads();
+        if (lane_id() == WAVE - 1)
+            red[wave_id()] = incl_max;
+        __syncthreads();
+        if (lane_id() == 0)
+            floor_v = wave_id() == 0 ? carry : red[wave_id() - 1];
+        floor_v = fmax(floor_v, carry);
+#pragma unroll
+        for (int j = 0; j < FIN_CH; ++j) {
+            const int64_t b = pbase + (int64_t)tid * FIN_CH + j;
+            if (b < count)
+                out[b] = fmax(e[j], floor_v);
+        }
+        const double pass_max = red[NW - 1];
+        carry = fmax(carry + total, pass_max);
     }
-    const double chunk_max = b1 > b0 ? fmax(last, excl) : excl;
-    const double prev_max = block_incl_max_scan<NW>(chunk_max, red);
-    double floor_v = __shfl_up(prev_max, 1);
-    __syncthreads();
-    if (lane_id() == WAVE - 1)
-        red[wave_id()] = prev_max;
-    __syncthreads();
-    if (lane_id() == 0)
-        floor_v = wave_id() == 0 ? 0.0 : red[wave_id() - 1];
-    run = excl;
-    for (int64_t b = b0; b < b1; ++b) {
-        out[b] = fmax(run, floor_v);
-        run += val(b);
-    }
-    // the grand total, never below any offset
-    __syncthreads();
-    if (tid == nthr - 1)
-        red[0] = fmax(total, prev_max);
-    __syncthreads();
-    const double tot = red[0];
     if (tid == 0)
-        out[count] = tot;
-    __syncthreads();
-    return tot;
+        out[count] = carry;
+    return carry;
 }
 
 // ---------------------------------------------------------------------------
 // Normalisation (single workgroup): global max M, tile offsets of the
 // cumulative weights, S1 = sum exp(lw - M), S2 = sum exp(2 (lw - M)),
 // L = M + log S1, L2 = 2M + log S2, ESS = exp(2L - L2), dlogZ = L - L_prev,
-// decision ESS < tau N (tau >= 1 always, tau <= 0 never).
+// decision ESS < tau N (tau >= 1 always, tau <= 0 never).  When a move
+// carried the monitor partials of the previous step (mon_step >= 0), their
+// importance-sampling estimates are completed here as well.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FIN_TPB) void finalize_kernel(
+struct MonDest {
+    int32_t step;     // history row, or -1 when no monitor partials are pending
+    int rows;         // monitored rows (partial columns 1..rows; column 0 = sum w)
+    int hist_col;     // first history column receiving estimates
+    int hist_ncols;   // how many of the last rows go to the history
+    double *out;      // optional device output [rows]
+};
+
+__device__ void mon_combine(const double *__restrict__ mon, int64_t ntiles, const MonDest &d,
+                            double *__restrict__ hist, int64_t hist_len, double *red,
+                            double *col)
+{
+    constexpr int NW = FIN_PASS_TPB / WAVE;
+    for (int r = 0; r <= d.rows; ++r) {
+        double a = 0.0;
+        for (int64_t b = threadIdx.x; b < ntiles; b += FIN_PASS_TPB)
+            a += mon[(int64_t)r * ntiles + b];
+        a = block_sum<NW>(a, red);
+        if (threadIdx.x == 0)
+            col[r] = a;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < d.rows) {
+        const int r = threadIdx.x;
+        const double est = col[1 + r] / col[0];
+        if (d.out)
+            d.out[r] = est;
+        if (hist && d.step >= 0 && d.step < hist_len && r >= d.rows - d.hist_ncols)
+            hist[(int64_t)d.step * SMC_HIST_COLS + d.hist_col + (r - (d.rows - d.hist_ncols))] =
+                est;
+    }
+}
+
+__global__ __launch_bounds__(FIN_PASS_TPB) void finalize_kernel(
     const TilePartial *__restrict__ part, int64_t ntiles, int64_t n, double threshold,
     double *__restrict__ prefix, double *__restrict__ scalars, double *__restrict__ hist,
-    int64_t hist_len, int32_t step, int32_t *__restrict__ counters)
+    int64_t hist_len, int32_t step, int32_t *__restrict__ counters,
+    const double *__restrict__ mon, MonDest md)
 {
-    __shared__ double red[FIN_NW];
+    constexpr int NW = FIN_PASS_TPB / WAVE;
+    __shared__ double sv[FIN_LDS];
+    __shared__ double red[NW];
+    __shared__ double col[MON_STRIDE];
     const int tid = threadIdx.x;
     double m = -INFINITY;
-    for (int64_t b = tid; b < ntiles; b += FIN_TPB)
+    for (int64_t b = tid; b < ntiles; b += FIN_PASS_TPB)
         m = fmax(m, part[b].m);
-    const double M = block_max<FIN_NW>(m, red);
+    const double M = block_max<NW>(m, red);
     auto scale = [&](int64_t b) {
         const double mb = part[b].m;
         return mb > -INFINITY ? exp(mb - M) : 0.0;
     };
-    const double S1 = tile_offsets<FIN_NW>(
-        ntiles, [&](int64_t b) { return part[b].s1 * scale(b); }, prefix, red);
+    const double S1 = tile_offsets(
+        ntiles, [&](int64_t b) { return part[b].s1 * scale(b); }, prefix, sv, red);
     double s2 = 0.0;
-    for (int64_t b = tid; b < ntiles; b += FIN_TPB) {
+    for (int64_t b = tid; b < ntiles; b += FIN_PASS_TPB) {
         const double sc = scale(b);
         s2 += part[b].s2 * (sc * sc);
     }
-    const double S2 = block_sum<FIN_NW>(s2, red);
+    const double S2 = block_sum<NW>(s2, red);
+    if (md.step >= 0)
+        mon_combine(mon, ntiles, md, hist, hist_len, red, col);
     if (tid == 0) {
         const double L = M + log(S1);
         const double L2 = 2.0 * M + log(S2);
@@ -162,11 +211,31 @@ __global__ __launch_bounds__(FIN_TPB) void finalize_kernel(
     }
 }
 
+static MonDest mon_dest(const Ctx &c, int32_t step, int rows, double *out)
+{
+    MonDest d;
+    d.step = step;
+    d.rows = rows;
+    d.out = out;
+    if (c.cfg.model == SMC_MODEL_CV_TRACK) {
+        d.hist_col = SMC_H_MON;
+        d.hist_ncols = rows;
+    } else {
+        d.hist_col = SMC_H_PATH;  // the last monitored row is the log-likelihood
+        d.hist_ncols = 1;
+    }
+    return d;
+}
+
 hipError_t launch_finalize(Ctx &c, int32_t step)
 {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_TPB), 0, c.stream, c.partials(),
+    MonDest md = mon_dest(c, c.mon_pending_step, c.mon_pending_rows, c.mon_pending_out);
+    if (c.mon_pending_step < 0)
+        md.step = -1;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_PASS_TPB), 0, c.stream, c.partials(),
                        c.ntiles, c.n, c.cfg.threshold, c.prefix(), c.buf.scalars, c.buf.history,
-                       c.buf.history_len, step, c.counters());
+                       c.buf.history_len, step, c.counters(), c.mon(), md);
+    c.mon_pending_step = -1;
     return hipGetLastError();
 }
 
@@ -405,16 +474,15 @@ __global__ __launch_bounds__(TPB) void mn_tile_sum_kernel(const double *__restri
         gtile[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(FIN_TPB) void mn_prefix_kernel(const double *__restrict__ scalars,
-                                                            int32_t force,
-                                                            const double *__restrict__ gtile,
-                                                            int64_t gtiles,
-                                                            double *__restrict__ gprefix)
+__global__ __launch_bounds__(FIN_PASS_TPB) void mn_prefix_kernel(
+    const double *__restrict__ scalars, int32_t force, const double *__restrict__ gtile,
+    int64_t gtiles, double *__restrict__ gprefix)
 {
-    __shared__ double red[FIN_NW];
+    __shared__ double sv[FIN_LDS];
+    __shared__ double red[FIN_PASS_TPB / WAVE];
     if (!(force != 0 || scalars[SMC_S_FLAG] != 0.0))
         return;
-    tile_offsets<FIN_NW>(gtiles, [&](int64_t b) { return gtile[b]; }, gprefix, red);
+    tile_offsets(gtiles, [&](int64_t b) { return gtile[b]; }, gprefix, sv, red);
 }
 
 __global__ __launch_bounds__(TPB) void mn_write_kernel(const double *__restrict__ scalars,
@@ -465,7 +533,7 @@ hipError_t launch_resample(Ctx &c, int32_t step, int32_t force)
         const int64_t count = c.n + 1;
         hipLaunchKernelGGL(mn_tile_sum_kernel, dim3((unsigned)c.gtiles), dim3(TPB), 0, c.stream,
                            c.buf.scalars, force, count, key, (uint32_t)step, p, c.gtile());
-        hipLaunchKernelGGL(mn_prefix_kernel, dim3(1), dim3(FIN_TPB), 0, c.stream, c.buf.scalars,
+        hipLaunchKernelGGL(mn_prefix_kernel, dim3(1), dim3(FIN_PASS_TPB), 0, c.stream, c.buf.scalars,
                            force, c.gtile(), c.gtiles, c.gprefix());
         hipLaunchKernelGGL(mn_write_kernel, dim3((unsigned)c.gtiles), dim3(TPB), 0, c.stream,
                            c.buf.scalars, force, count, key, (uint32_t)step, p, c.gprefix(),
@@ -481,13 +549,14 @@ hipError_t launch_resample(Ctx &c, int32_t step, int32_t force)
 
 // ---------------------------------------------------------------------------
 // Monitors: per-tile sums of w_i and w_i x_r,i (w_i = exp(lw_i - M), or 1
-// after a resample), then one workgroup combines the tiles in order.
+// after a resample), column-major [1 + rows][ntiles], then one workgroup
+// combines the tiles in a fixed order.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(TPB) void mon_partial_kernel(
     const T *__restrict__ x, int rows, int64_t n, const double *__restrict__ lw,
     const int32_t *__restrict__ anc, const double *__restrict__ scalars, int gather_check,
-    int reset_check, double *__restrict__ mon)
+    int reset_check, double *__restrict__ mon, int64_t ntiles)
 {
     __shared__ double red[NWAVES];
     const bool resampled = scalars[SMC_S_RESAMPLED] != 0.0;
@@ -507,11 +576,10 @@ __global__ __launch_bounds__(TPB) void mon_partial_kernel(
             w[k] = reset ? 1.0 : (lw[i] > -INFINITY ? exp(lw[i] - M) : 0.0);
         }
     }
-    double* out = mon + (int64_t)blockIdx.x * MON_STRIDE;
     double sw = w[0] + w[1] + w[2] + w[3];
     sw = block_sum<NWAVES>(sw, red);
     if (threadIdx.x == 0)
-        out[0] = sw;
+        mon[blockIdx.x] = sw;
     for (int r = 0; r < rows; ++r) {
         double s = 0.0;
 #pragma unroll
@@ -520,38 +588,18 @@ __global__ __launch_bounds__(TPB) void mon_partial_kernel(
                 s += w[k] * (double)x[(int64_t)r * n + src[k]];
         s = block_sum<NWAVES>(s, red);
         if (threadIdx.x == 0)
-            out[1 + r] = s;
+            mon[(int64_t)(1 + r) * ntiles + blockIdx.x] = s;
     }
 }
 
-__global__ __launch_bounds__(TPB) void mon_final_kernel(const double *__restrict__ mon,
-                                                        int64_t ntiles, int rows, int32_t step,
-                                                        double *__restrict__ hist,
-                                                        int64_t hist_len, int hist_col,
-                                                        int hist_ncols, double *__restrict__ out)
+__global__ __launch_bounds__(FIN_PASS_TPB) void mon_final_kernel(const double *__restrict__ mon,
+                                                                 int64_t ntiles, MonDest md,
+                                                                 double *__restrict__ hist,
+                                                                 int64_t hist_len)
 {
-    __shared__ double red[NWAVES];
+    __shared__ double red[FIN_PASS_TPB / WAVE];
     __shared__ double col[MON_STRIDE];
-    for (int r = 0; r <= rows; ++r) {
-        const int64_t chunk = ceil_div(ntiles, TPB);
-        const int64_t b0 = min((int64_t)threadIdx.x * chunk, ntiles);
-        const int64_t b1 = min(b0 + chunk, ntiles);
-        double s = 0.0;
-        for (int64_t b = b0; b < b1; ++b)
-            s += mon[b * MON_STRIDE + r];
-        s = block_sum<NWAVES>(s, red);
-        if (threadIdx.x == 0)
-            col[r] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < rows) {
-        const int r = threadIdx.x;
-        const double est = col[1 + r] / col[0];
-        if (out)
-            out[r] = est;
-        if (hist && step >= 0 && step < hist_len && r >= rows - hist_ncols)
-            hist[(int64_t)step * SMC_HIST_COLS + hist_col + (r - (rows - hist_ncols))] = est;
-    }
+    mon_combine(mon, ntiles, md, hist, hist_len, red, col);
 }
 
 hipError_t launch_monitor(Ctx &c, int32_t step, double *out_dev, int rows, bool gather_pending,
@@ -562,23 +610,15 @@ hipError_t launch_monitor(Ctx &c, int32_t step, double *out_dev, int rows, bool 
         hipLaunchKernelGGL(mon_partial_kernel<float>, grid, dim3(TPB), 0, c.stream,
                            (const float *)c.state_ptr(), rows, c.n, c.buf.log_weight,
                            c.buf.ancestors, c.buf.scalars, (int)gather_pending,
-                           (int)reset_pending, c.mon());
+                           (int)reset_pending, c.mon(), c.ntiles);
     else
         hipLaunchKernelGGL(mon_partial_kernel<double>, grid, dim3(TPB), 0, c.stream,
                            (const double *)c.state_ptr(), rows, c.n, c.buf.log_weight,
                            c.buf.ancestors, c.buf.scalars, (int)gather_pending,
-                           (int)reset_pending, c.mon());
-    int hist_col, hist_ncols;
-    if (c.cfg.model == SMC_MODEL_CV_TRACK) {
-        hist_col = SMC_H_MON;
-        hist_ncols = rows;
-    } else {
-        hist_col = SMC_H_PATH;  // the last monitored row is the log-likelihood
-        hist_ncols = 1;
-    }
-    hipLaunchKernelGGL(mon_final_kernel, dim3(1), dim3(TPB), 0, c.stream, c.mon(), c.ntiles,
-                       rows, step, c.buf.history, c.buf.history_len, hist_col, hist_ncols,
-                       out_dev);
+                           (int)reset_pending, c.mon(), c.ntiles);
+    const MonDest md = mon_dest(c, step, rows, out_dev);
+    hipLaunchKernelGGL(mon_final_kernel, dim3(1), dim3(FIN_PASS_TPB), 0, c.stream, c.mon(),
+                       c.ntiles, md, c.buf.history, c.buf.history_len);
     return hipGetLastError();
 }
 

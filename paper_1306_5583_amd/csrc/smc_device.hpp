@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "smc_math.hpp"
+
 namespace smc {
 
 constexpr int WAVE = 64;
@@ -50,16 +52,15 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     uint32_t k0 = key.k0, k1 = key.k1;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        // one 32x32->64 multiply per product (v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo1;
+        c1 = (uint32_t)p1;
         c2 = n2;
-        c3 = lo0;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -84,14 +85,15 @@ __device__ __forceinline__ float u24(uint32_t w)
     return (float)((w >> 8) + 1u) * 0x1p-24f;
 }
 
-// Box-Muller: two standard normals from the four words of one call.
+// Box-Muller: two standard normals from the four words of one call,
+// r = sqrt(-2 log u1), angle 2 pi u2 (sin/cos of pi * (2 u2), exact argument).
 __device__ __forceinline__ double2 normal2(uint4 w)
 {
     const double u1 = u53(w.x, w.y);
     const double u2 = u53(w.z, w.w);
-    const double r = sqrt(-2.0 * log(u1));
+    const double r = sqrt(-2.0 * log_d(u1));
     double s, c;
-    sincos(kTwoPi * u2, &s, &c);
+    sincospi_d(u2 + u2, &s, &c);
     return make_double2(r * c, r * s);
 }
 
@@ -100,9 +102,11 @@ __device__ __forceinline__ float4 normal4f(uint4 w)
 {
     float s0, c0, s1, c1;
     const float r0 = sqrtf(-2.0f * logf(u24(w.x)));
-    sincosf(kTwoPiF * u24(w.y), &s0, &c0);
+    const float a0 = u24(w.y);
+    sincospif(a0 + a0, &s0, &c0);
     const float r1 = sqrtf(-2.0f * logf(u24(w.z)));
-    sincosf(kTwoPiF * u24(w.w), &s1, &c1);
+    const float a1 = u24(w.w);
+    sincospif(a1 + a1, &s1, &c1);
     return make_float4(r0 * c0, r0 * s0, r1 * c1, r1 * s1);
 }
 
@@ -241,6 +245,29 @@ __device__ __forceinline__ double block_incl_scan(double v, double *red, double 
     }
     *total = all;
     return before + v;
+}
+
+// Exclusive prefix sum across the workgroup, defined as the inclusive value
+// of the previous lane so that consecutive lanes agree exactly; *total
+// receives the sum (sequential over the wave totals).
+template <int NW>
+__device__ __forceinline__ double block_excl_scan(double v, double *red, double *total)
+{
+    const double incl = wave_incl_scan(v);
+    double excl = __shfl_up(incl, 1);
+    __syncthreads();
+    if (lane_id() == WAVE - 1)
+        red[wave_id()] = incl;
+    __syncthreads();
+    double before = 0.0, all = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (w < wave_id())
+            before += red[w];
+        all += red[w];
+    }
+    *total = all;
+    return lane_id() == 0 ? before : before + excl;
 }
 
 // Inclusive prefix max across the workgroup (exact, order-free).

@@ -45,6 +45,11 @@ struct Ctx {
     // flag) has not yet been applied to the log-weights / the state.
     bool armed_lw = false;
     bool armed_gather = false;
+    // Monitor partials produced by a move for an earlier step, completed by
+    // the next normalisation (-1: none pending).
+    int32_t mon_pending_step = -1;
+    int mon_pending_rows = 0;
+    double *mon_pending_out = nullptr;
     // Student-t / Gaussian observation constants (CV).
     double obs_const = 0.0;
     double obs_half_nu1 = 0.0;
@@ -80,7 +85,7 @@ hipError_t launch_draw_words(uint64_t seed, uint32_t t, uint32_t tag, uint32_t j
 // --- CV model launchers (smc_pf.hip) ---
 hipError_t launch_pf_init(Ctx &c);
 hipError_t launch_pf_move(Ctx &c, int32_t step, int32_t obs_index, bool fuse, bool gather_check,
-                          bool reset_check);
+                          bool reset_check, bool monitor);
 hipError_t launch_pf_reweight(Ctx &c, int32_t obs_index, bool reset_check);
 
 // --- GMM launchers (smc_gmm.hip) ---

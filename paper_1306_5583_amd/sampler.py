@@ -104,28 +104,38 @@ class ParticleFilter(_Base):
         super().__init__(cfg, y, T, device, stream)
         self._margs = L.smc_move_args()
         self._margs.fuse_reweight = 1
+        self._mon_pending = -1
 
     def init(self, monitor: bool = True):
         L.smc_init(self.ctx)
         L.smc_ess(self.ctx, 0)
         L.smc_resample(self.ctx, 0)
-        if monitor:
-            L.smc_monitor(self.ctx, 0)
+        self._mon_pending = 0 if monitor else -1
 
     def step(self, t: int, monitor: bool = True):
-        """One iteration: move + weight (fused), normalise, resample if
-        ESS < threshold N, monitor."""
-        self._margs.obs_index = t
-        L.smc_move(self.ctx, t, self._margs)
+        """One iteration: move + weight (fused, also completing the monitor
+        of the previous step from the same pass), normalise, resample if
+        ESS < threshold N.  The monitor of step t is carried by the next
+        move; finish() completes the last one."""
+        m = self._margs
+        m.obs_index = t
+        m.monitor_step = self._mon_pending
+        L.smc_move(self.ctx, t, m)
         L.smc_ess(self.ctx, t)
         L.smc_resample(self.ctx, t)
-        if monitor:
-            L.smc_monitor(self.ctx, t)
+        self._mon_pending = t if monitor else -1
+
+    def finish(self):
+        """Completes a monitor still pending after the last step."""
+        if self._mon_pending >= 0:
+            L.smc_monitor(self.ctx, self._mon_pending)
+            self._mon_pending = -1
 
     def run(self, monitor: bool = True) -> float:
         self.init(monitor)
         for t in range(1, self.T):
             self.step(t, monitor)
+        self.finish()
         return self.log_z()
 
     def history_host(self) -> np.ndarray:

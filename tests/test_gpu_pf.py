@@ -208,9 +208,36 @@ def test_unfused_reweight_matches_fused(lib):
         L.smc_ess(b.ctx, t)
         L.smc_resample(b.ctx, t)
         L.smc_monitor(b.ctx, t)
+    a.finish()
     torch.cuda.synchronize()
-    assert np.array_equal(a.history_host(), b.history_host())
+    ha, hb = a.history_host(), b.history_host()
+    assert np.array_equal(ha[:, :L.SMC_H_MON], hb[:, :L.SMC_H_MON])
+    # a's monitors come from the fused sweep, b's from the standalone kernels
+    assert_close_l1(ha[:, L.SMC_H_MON:L.SMC_H_MON + 4], hb[:, L.SMC_H_MON:L.SMC_H_MON + 4], 20.0,
+                    1e-14, "fused monitor")
     assert torch.equal(a.state(), b.state()) and torch.equal(a.log_weight, b.log_weight)
+
+
+@pytest.mark.parametrize("fp32,threshold", [(False, 0.5), (True, 0.5), (False, 0.0)])
+def test_fused_monitor_matches_standalone(lib, fp32, threshold):
+    pkg, L = lib
+    _, y = synth.pf_trajectory(30, 5)
+    a = pkg.ParticleFilter(9000, y, seed=4, fp32_state=fp32, threshold=threshold)
+    b = pkg.ParticleFilter(9000, y, seed=4, fp32_state=fp32, threshold=threshold)
+    a.run()
+    b.init()
+    L.smc_monitor(b.ctx, 0)
+    for t in range(1, 30):
+        m = L.smc_move_args()
+        m.obs_index, m.fuse_reweight = t, 1
+        L.smc_move(b.ctx, t, m)
+        L.smc_ess(b.ctx, t)
+        L.smc_resample(b.ctx, t)
+        L.smc_monitor(b.ctx, t)
+    ha, hb = a.history_host(), b.history_host()
+    assert np.array_equal(ha[:, :L.SMC_H_MON], hb[:, :L.SMC_H_MON])
+    assert_close_l1(ha[:, L.SMC_H_MON:L.SMC_H_MON + 4], hb[:, L.SMC_H_MON:L.SMC_H_MON + 4], 20.0,
+                    1e-14, "fused monitor")
 
 
 def test_gather_materialises_state(lib, orc):
