@@ -35,73 +35,96 @@ hipError_t launch_reset_scalars(Ctx &c)
 }
 
 // ---------------------------------------------------------------------------
-// Cumulative offsets of `count` non-negative tile values v_b (computed by
-// `val(b)`) in one workgroup of FIN_PASS_TPB lanes: out[b] = sum_{b' < b} v_b',
-// out[count] = total.  Values are staged through LDS in passes of FIN_PASS;
-// each lane sums a contiguous chunk of FIN_CH values sequentially, the
-// chunk totals are scanned across the workgroup in a fixed order, and an
+// Cumulative offsets of `count` non-negative tile values v_b in one
+// workgroup of FIN_TPB lanes: out[b] = sum_{b' < b} v_b', out[count] = total.
+// Passes of FIN_PASS values; in a pass lane t owns the FIN_IT consecutive
+// values starting at FIN_IT t (all loaded at once), sums them sequentially,
+// the lane totals are scanned across the workgroup in a fixed order, and an
 // exact running maximum keeps out[] non-decreasing.  The same inputs always
-// give the same outputs.
+// give the same outputs.  `val(b)` is called exactly once per b, in
+// increasing b for each lane.
 // ---------------------------------------------------------------------------
-constexpr int FIN_CH = 16;
-constexpr int FIN_PASS_TPB = 256;
-constexpr int FIN_PASS = FIN_PASS_TPB * FIN_CH;
-constexpr int FIN_LDS = FIN_PASS_TPB * (FIN_CH + 1);  // padded chunks: no bank conflicts
+constexpr int FIN_TPB = 1024;
+constexpr int FIN_NW = FIN_TPB / WAVE;
+constexpr int FIN_IT = 4;
+constexpr int FIN_PASS = FIN_TPB * FIN_IT;
 
-__device__ __forceinline__ int fin_pidx(int j) { return (j / FIN_CH) * (FIN_CH + 1) + j % FIN_CH; }
+// One pass: lane values v[] for b0 .. b0+FIN_IT-1; returns the new carry.
+__device__ __forceinline__ double offsets_pass(const double (&v)[FIN_IT], int64_t b0,
+                                               int64_t count, double carry, double *out,
+                                               double *red)
+{
+    double e[FIN_IT];
+    double run = 0.0;
+#pragma unroll
+    for (int k = 0; k < FIN_IT; ++k) {
+        e[k] = run;
+        run += v[k];
+    }
+    double total;
+    const double excl = block_excl_scan<FIN_NW>(run, red, &total);
+    double last = 0.0;
+#pragma unroll
+    for (int k = 0; k < FIN_IT; ++k) {
+        e[k] = carry + (excl + e[k]);
+        last = fmax(last, e[k]);
+    }
+    const double incl_max = block_incl_max_scan<FIN_NW>(last, red);
+    double floor_v = __shfl_up(incl_max, 1);
+    __syncthreads();
+    if (lane_id() == WAVE - 1)
+        red[wave_id()] = incl_max;
+    __syncthreads();
+    if (lane_id() == 0)
+        floor_v = wave_id() == 0 ? carry : red[wave_id() - 1];
+    floor_v = fmax(floor_v, carry);
+#pragma unroll
+    for (int k = 0; k < FIN_IT; ++k)
+        if (b0 + k < count)
+            out[b0 + k] = fmax(e[k], floor_v);
+    const double pass_max = red[FIN_NW - 1];
+    __syncthreads();
+    return fmax(carry + total, pass_max);
+}
 
 template <typename F>
-__device__ double tile_offsets(int64_t count, F val, double *out, double *sv, double *red)
+__device__ double tile_offsets(int64_t count, F val, double *out, double *red)
 {
-    constexpr int NW = FIN_PASS_TPB / WAVE;
-    const int tid = threadIdx.x;
     double carry = 0.0;
     for (int64_t pbase = 0; pbase < count; pbase += FIN_PASS) {
-        __syncthreads();
-#pragma unroll 4
-        for (int k = 0; k < FIN_CH; ++k) {
-            const int j = k * FIN_PASS_TPB + tid;
-            const int64_t b = pbase + j;
-            sv[fin_pidx(j)] = b < count ? val(b) : 0.0;
-        }
-        __syncthreads();
-        double e[FIN_CH];
-        double run = 0.0;
+        const int64_t b0 = pbase + (int64_t)threadIdx.x * FIN_IT;
+        double v[FIN_IT];
 #pragma unroll
-        for (int j = 0; j < FIN_CH; ++j) {
-            e[j] = run;
-            run += sv[tid * (FIN_CH + 1) + j];
-        }
-        double total;
-        const double excl = block_excl_scan<NW>(run, red, &total);
-        // candidate offsets, then the exact floor from all earlier chunks
-        double last = 0.0;
-#pragma unroll
-        for (int j = 0; j < FIN_CH; ++j) {
-            e[j] = carry + (excl + e[j]);
-            last = fmax(last, e[j]);
-        }
-        const double incl_max = block_incl_max_scan<NW>(last, red);
-        double floor_v = __shfl_up(incl_max, 1);
-        __syncthreads();
-        if (lane_id() == WAVE - 1)
-            red[wave_id()] = incl_max;
-        __syncthreads();
-        if (lane_id() == 0)
-            floor_v = wave_id() == 0 ? carry : red[wave_id() - 1];
-        floor_v = fmax(floor_v, carry);
-#pragma unroll
-        for (int j = 0; j < FIN_CH; ++j) {
-            const int64_t b = pbase + (int64_t)tid * FIN_CH + j;
-            if (b < count)
-                out[b] = fmax(e[j], floor_v);
-        }
-        const double pass_max = red[NW - 1];
-        carry = fmax(carry + total, pass_max);
+        for (int k = 0; k < FIN_IT; ++k)
+            v[k] = b0 + k < count ? val(b0 + k) : 0.0;
+        carry = offsets_pass(v, b0, count, carry, out, red);
     }
-    if (tid == 0)
+    if (threadIdx.x == 0)
         out[count] = carry;
     return carry;
+}
+
+// Workgroup sums of R values at once (one pair of barriers).
+template <int NW, int R>
+__device__ __forceinline__ void block_sum_multi(double (&v)[R], double *red /* NW*R */)
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        v[r] = wave_sum(v[r]);
+    __syncthreads();
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            red[wave_id() * R + r] = v[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double a = red[r];
+        for (int w = 1; w < NW; ++w)
+            a += red[w * R + r];
+        v[r] = a;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -120,15 +143,25 @@ struct MonDest {
     double *out;      // optional device output [rows]
 };
 
+template <int NTHR>
 __device__ void mon_combine(const double *__restrict__ mon, int64_t ntiles, const MonDest &d,
                             double *__restrict__ hist, int64_t hist_len, double *red,
                             double *col)
 {
-    constexpr int NW = FIN_PASS_TPB / WAVE;
+    constexpr int NW = NTHR / WAVE;
     for (int r = 0; r <= d.rows; ++r) {
+        const double *m = mon + (int64_t)r * ntiles;
         double a = 0.0;
-        for (int64_t b = threadIdx.x; b < ntiles; b += FIN_PASS_TPB)
-            a += mon[(int64_t)r * ntiles + b];
+        int64_t b = threadIdx.x;
+        for (; b + 3 * NTHR < ntiles; b += 4 * NTHR) {
+            const double x0 = m[b], x1 = m[b + NTHR], x2 = m[b + 2 * NTHR], x3 = m[b + 3 * NTHR];
+            a += x0;
+            a += x1;
+            a += x2;
+            a += x3;
+        }
+        for (; b < ntiles; b += NTHR)
+            a += m[b];
         a = block_sum<NW>(a, red);
         if (threadIdx.x == 0)
             col[r] = a;
@@ -145,35 +178,89 @@ __device__ void mon_combine(const double *__restrict__ mon, int64_t ntiles, cons
     }
 }
 
-__global__ __launch_bounds__(FIN_PASS_TPB) void finalize_kernel(
+constexpr int FIN_MON_ROWS = 4;  // rows a move can carry (the tracking state)
+
+__global__ __launch_bounds__(FIN_TPB) void finalize_kernel(
     const TilePartial *__restrict__ part, int64_t ntiles, int64_t n, double threshold,
     double *__restrict__ prefix, double *__restrict__ scalars, double *__restrict__ hist,
     int64_t hist_len, int32_t step, int32_t *__restrict__ counters,
     const double *__restrict__ mon, MonDest md)
 {
-    constexpr int NW = FIN_PASS_TPB / WAVE;
-    __shared__ double sv[FIN_LDS];
-    __shared__ double red[NW];
+    __shared__ double red[FIN_NW * (FIN_MON_ROWS + 2)];
     __shared__ double col[MON_STRIDE];
     const int tid = threadIdx.x;
-    double m = -INFINITY;
-    for (int64_t b = tid; b < ntiles; b += FIN_PASS_TPB)
-        m = fmax(m, part[b].m);
-    const double M = block_max<NW>(m, red);
-    auto scale = [&](int64_t b) {
-        const double mb = part[b].m;
-        return mb > -INFINITY ? exp(mb - M) : 0.0;
-    };
-    const double S1 = tile_offsets(
-        ntiles, [&](int64_t b) { return part[b].s1 * scale(b); }, prefix, sv, red);
-    double s2 = 0.0;
-    for (int64_t b = tid; b < ntiles; b += FIN_PASS_TPB) {
-        const double sc = scale(b);
-        s2 += part[b].s2 * (sc * sc);
+    double M, S1, S2;
+    if (ntiles <= FIN_PASS) {
+        // one pass: every load of this lane is issued up front
+        const int64_t b0 = (int64_t)tid * FIN_IT;
+        TilePartial q[FIN_IT];
+        double mo[FIN_MON_ROWS + 1][FIN_IT];
+#pragma unroll
+        for (int k = 0; k < FIN_IT; ++k) {
+            const bool ok = b0 + k < ntiles;
+            q[k] = ok ? part[b0 + k] : TilePartial{-INFINITY, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r <= FIN_MON_ROWS; ++r)
+                mo[r][k] = (ok && md.step >= 0 && r <= md.rows) ? mon[(int64_t)r * ntiles + b0 + k]
+                                                                : 0.0;
+        }
+        double m = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < FIN_IT; ++k)
+            m = fmax(m, q[k].m);
+        M = block_max<FIN_NW>(m, red);
+        double v[FIN_IT];
+        double s2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < FIN_IT; ++k) {
+            const double sc = q[k].m > -INFINITY ? exp(q[k].m - M) : 0.0;
+            v[k] = q[k].s1 * sc;
+            s2 += q[k].s2 * (sc * sc);
+        }
+        S1 = offsets_pass(v, b0, ntiles, 0.0, prefix, red);
+        if (tid == 0)
+            prefix[ntiles] = S1;
+        double acc[FIN_MON_ROWS + 2];
+        acc[0] = s2;
+#pragma unroll
+        for (int r = 0; r <= FIN_MON_ROWS; ++r)
+            acc[1 + r] = ((mo[r][0] + mo[r][1]) + mo[r][2]) + mo[r][3];
+        block_sum_multi<FIN_NW, FIN_MON_ROWS + 2>(acc, red);
+        S2 = acc[0];
+        if (md.step >= 0 && tid < md.rows) {
+            const double est = acc[2 + tid] / acc[1];
+            if (md.out)
+                md.out[tid] = est;
+            if (hist && md.step < hist_len && tid >= md.rows - md.hist_ncols)
+                hist[(int64_t)md.step * SMC_HIST_COLS + md.hist_col +
+                     (tid - (md.rows - md.hist_ncols))] = est;
+        }
+    } else {
+        double m = -INFINITY;
+        for (int64_t b = (int64_t)tid * FIN_IT; b < ntiles; b += FIN_PASS) {
+            double qm[FIN_IT];
+#pragma unroll
+            for (int k = 0; k < FIN_IT; ++k)
+                qm[k] = b + k < ntiles ? part[b + k].m : -INFINITY;
+#pragma unroll
+            for (int k = 0; k < FIN_IT; ++k)
+                m = fmax(m, qm[k]);
+        }
+        M = block_max<FIN_NW>(m, red);
+        double s2 = 0.0;
+        S1 = tile_offsets(
+            ntiles,
+            [&](int64_t b) {
+                const TilePartial q = part[b];
+                const double sc = q.m > -INFINITY ? exp(q.m - M) : 0.0;
+                s2 += q.s2 * (sc * sc);
+                return q.s1 * sc;
+            },
+            prefix, red);
+        S2 = block_sum<FIN_NW>(s2, red);
+        if (md.step >= 0)
+            mon_combine<FIN_TPB>(mon, ntiles, md, hist, hist_len, red, col);
     }
-    const double S2 = block_sum<NW>(s2, red);
-    if (md.step >= 0)
-        mon_combine(mon, ntiles, md, hist, hist_len, red, col);
     if (tid == 0) {
         const double L = M + log(S1);
         const double L2 = 2.0 * M + log(S2);
@@ -232,7 +319,7 @@ hipError_t launch_finalize(Ctx &c, int32_t step)
     MonDest md = mon_dest(c, c.mon_pending_step, c.mon_pending_rows, c.mon_pending_out);
     if (c.mon_pending_step < 0)
         md.step = -1;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_PASS_TPB), 0, c.stream, c.partials(),
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_TPB), 0, c.stream, c.partials(),
                        c.ntiles, c.n, c.cfg.threshold, c.prefix(), c.buf.scalars, c.buf.history,
                        c.buf.history_len, step, c.counters(), c.mon(), md);
     c.mon_pending_step = -1;
@@ -326,17 +413,103 @@ __device__ int64_t count_below_search(const P &pred, double x, int64_t n)
     return lo + (__ffsll((long long)bal) - 1);
 }
 
+// Cumulative weights of one tile in the blocked arrangement: lane t owns the
+// four consecutive particles base + 4t .. base + 4t + 3.  Returns S for those
+// four and, in s_prev, S of the particle before the first (Pb for lane 0).
+// S is clamped into [Pb, Pb1] and, from the tile's last positive-weight
+// particle on, equals Pb1 exactly, so consecutive tiles join without gaps or
+// overlaps and a zero-weight particle never owns a slot.
+struct TileCdf {
+    double S[ITEMS];
+    double s_prev;
+    int lastpos;  // tile-local index of the last positive-weight particle, -1 if none
+};
+
+__device__ __forceinline__ TileCdf tile_cdf(const double *__restrict__ lw, int64_t base, int len,
+                                            double mb, double sc, double Pb, double Pb1,
+                                            double *red, double *wave_last, int *wave_pos)
+{
+    const int tid = threadIdx.x;
+    const int j0 = ITEMS * tid;
+    double l[ITEMS];
+    if (j0 + ITEMS <= len) {
+        const double4 q = *reinterpret_cast<const double4 *>(lw + base + j0);
+        l[0] = q.x;
+        l[1] = q.y;
+        l[2] = q.z;
+        l[3] = q.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+            l[k] = j0 + k < len ? lw[base + j0 + k] : -INFINITY;
+    }
+    double a[ITEMS];
+    double run = 0.0;
+    int lastpos = -1;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const double w = (l[k] > -INFINITY && mb > -INFINITY) ? exp(l[k] - mb) : 0.0;
+        run += w;
+        a[k] = run;
+        lastpos = w > 0.0 ? j0 + k : lastpos;
+    }
+#pragma unroll
+    for (int off = WAVE / 2; off >= 1; off >>= 1)
+        lastpos = max(lastpos, __shfl_xor(lastpos, off));
+    if (lane_id() == 0)
+        wave_pos[wave_id()] = lastpos;
+    double total;
+    const double excl = block_excl_scan<NWAVES>(run, red, &total);  // synchronises
+#pragma unroll
+    for (int w = 0; w < NWAVES; ++w)
+        lastpos = max(lastpos, wave_pos[w]);
+    TileCdf r;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int j = j0 + k;
+        r.S[k] = j < lastpos ? fmin(Pb + (excl + a[k]) * sc, Pb1) : Pb1;
+    }
+    if (lastpos < 0) {  // no positive weight in the tile: Pb == Pb1
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+            r.S[k] = Pb;
+    }
+    // S of the previous particle: the neighbouring lane's last value
+    double prev = __shfl_up(r.S[ITEMS - 1], 1);
+    __syncthreads();
+    if (lane_id() == WAVE - 1)
+        wave_last[wave_id()] = r.S[ITEMS - 1];
+    __syncthreads();
+    if (lane_id() == 0)
+        prev = wave_id() == 0 ? Pb : wave_last[wave_id() - 1];
+    r.s_prev = prev;
+    r.lastpos = lastpos;
+    return r;
+}
+
+// Sorted ancestors of one tile by a merge of two sorted sequences: the
+// tile's cumulative weights S_j and the ordered uniforms u_i of the slots it
+// owns, [c(Pb), c(Pb1)) with c(x) = #{i : u_i S < x} (to N for the tile
+// holding the last positive weight).  Slot i goes to the first j with
+// S_j > u_i S.  Each lane takes an equal share of the merged sequence,
+// finds its start by a merge-path search, then walks it: the work is
+// balanced however unevenly the slots fall on the particles.  Slot uniforms
+// are staged in LDS when the tile owns at most RS_UCAP slots.
+constexpr int RS_UCAP = 2048;
+
 template <int SCHEME>
-__global__ __launch_bounds__(TPB) void resample_kernel(
+__global__ __launch_bounds__(TPB) void resample_merge_kernel(
     const double *__restrict__ lw, const TilePartial *__restrict__ part,
     const double *__restrict__ prefix, int64_t n, int64_t ntiles, double *__restrict__ scalars,
     int32_t *__restrict__ anc, Key key, uint32_t t, uint32_t p, int32_t force,
     const double *__restrict__ G, int32_t *__restrict__ counters)
 {
     __shared__ double sS[TILE];
+    __shared__ double sU[RS_UCAP];
     __shared__ double red[NWAVES];
+    __shared__ double wave_last[NWAVES];
+    __shared__ int wave_pos[NWAVES];
     __shared__ long long rng_lohi[2];
-    __shared__ int jstar_sh;
     const int tid = threadIdx.x;
     const bool go = force != 0 || scalars[SMC_S_FLAG] != 0.0;
     const uint4 wU = draw(key, 0, t, TAG_RESAMPLE, 0, p);
@@ -361,86 +534,77 @@ __global__ __launch_bounds__(TPB) void resample_kernel(
     const double Pb = prefix[b], Pb1 = prefix[b + 1];
     const double mb = part[b].m;
     const double sc = mb > -INFINITY ? exp(mb - M) : 0.0;
-
-    double carry = 0.0;
+    const TileCdf cdf = tile_cdf(lw, base, len, mb, sc, Pb, Pb1, red, wave_last, wave_pos);
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const int64_t i = base + k * TPB + tid;
-        double w = 0.0;
-        if (i < n) {
-            const double l = lw[i];
-            w = (l > -INFINITY && mb > -INFINITY) ? exp(l - mb) : 0.0;
-        }
-        double tot;
-        const double incl = block_incl_scan<NWAVES>(w, red, &tot);
-        sS[k * TPB + tid] = fmin(Pb + (carry + incl) * sc, Pb1);
-        carry += tot;
-    }
-    __syncthreads();
-    if (tid == 0)
-        sS[len - 1] = Pb1;
-    __syncthreads();
+    for (int k = 0; k < ITEMS; ++k)
+        sS[ITEMS * tid + k] = cdf.S[k];
 
-    const bool has_last = Pb < stot && Pb1 >= stot;
+    const SysPred sys{U, stot, n};
+    const StratPred strat{key, t, p, stot, n};
+    const MultiPred multi{G, SCHEME == SMC_RS_MULTINOMIAL ? G[n] : 1.0, stot, n};
+    auto pred = [&](int64_t i) -> double {
+        if (SCHEME == SMC_RS_SYSTEMATIC)
+            return sys(i);
+        if (SCHEME == SMC_RS_STRATIFIED)
+            return strat(i);
+        return multi(i);
+    };
+    const double nd = (double)n;
     if (SCHEME == SMC_RS_MULTINOMIAL) {
-        const MultiPred pred{G, G[n], stot, n};
         if (wave_id() < 2) {
-            const double x = wave_id() == 0 ? Pb : Pb1;
-            const int64_t cnt = count_below_search(pred, x, n);
+            const int64_t cnt = count_below_search(multi, wave_id() == 0 ? Pb : Pb1, n);
             if (lane_id() == 0)
                 rng_lohi[wave_id()] = cnt;
         }
     } else if (tid < 2) {
         const double x = tid == 0 ? Pb : Pb1;
-        int64_t cnt;
-        if (SCHEME == SMC_RS_SYSTEMATIC) {
-            const SysPred pred{U, stot, n};
-            cnt = count_below_walk(pred, x, n, ceil(x / stot * (double)n - U));
-        } else {
-            const StratPred pred{key, t, p, stot, n};
-            cnt = count_below_walk(pred, x, n, floor(x / stot * (double)n - 0.5));
-        }
-        rng_lohi[tid] = cnt;
-    }
-    if (tid == 0) {
-        // first element equal to the total: the last positive-weight particle
-        int lo = 0, hi = len - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (sS[mid] >= stot)
-                hi = mid;
-            else
-                lo = mid + 1;
-        }
-        jstar_sh = lo;
+        rng_lohi[tid] = SCHEME == SMC_RS_SYSTEMATIC
+                            ? count_below_walk(sys, x, n, ceil(x / stot * nd - U))
+                            : count_below_walk(strat, x, n, floor(x / stot * nd - 0.5));
     }
     __syncthreads();
+    const bool has_last = Pb < stot && Pb1 >= stot;
     const int64_t lo = rng_lohi[0];
-    const int64_t hi = has_last ? n : (int64_t)rng_lohi[1];
-    const int jstar = jstar_sh;
+    const int64_t hi = has_last ? n : max((int64_t)rng_lohi[1], lo);
+    const int64_t ns = hi - lo;
+    const int jstar = cdf.lastpos < 0 ? 0 : cdf.lastpos;
+    const bool staged = ns <= RS_UCAP;
+    if (staged)
+        for (int64_t q = tid; q < ns; q += TPB)
+            sU[q] = pred(lo + q);
+    __syncthreads();
+    auto u_at = [&](int64_t q) -> double { return staged ? sU[q] : pred(lo + q); };
 
-    for (int64_t i = lo + tid; i < hi; i += TPB) {
-        double x;
-        if (SCHEME == SMC_RS_SYSTEMATIC)
-            x = SysPred{U, stot, n}(i);
-        else if (SCHEME == SMC_RS_STRATIFIED)
-            x = StratPred{key, t, p, stot, n}(i);
+    const int64_t total = (int64_t)len + ns;
+    const int64_t ipt = ceil_div(total, TPB);
+    const int64_t d0 = min((int64_t)tid * ipt, total);
+    const int64_t d1 = min(d0 + ipt, total);
+    // merge-path split of the first d0 items: owners consumed = first j with
+    // S_j not preceding slot d0-1-j  (an owner precedes a slot iff S_j <= u)
+    int64_t jl = max((int64_t)0, d0 - ns), jh = min(d0, (int64_t)len);
+    while (jl < jh) {
+        const int64_t mid = (jl + jh) >> 1;
+        if (sS[mid] <= u_at(d0 - 1 - mid))
+            jl = mid + 1;
         else
-            x = MultiPred{G, G[n], stot, n}(i);
-        int l = 0, h = len;  // first j with sS[j] > x
-        while (l < h) {
-            const int mid = (l + h) >> 1;
-            if (sS[mid] > x)
-                h = mid;
-            else
-                l = mid + 1;
+            jh = mid;
+    }
+    int64_t j = jl, i = d0 - jl;
+    double uj = i < ns ? u_at(i) : 0.0;
+    for (int64_t s = d0; s < d1; ++s) {
+        if (j < len && (i >= ns || sS[j] <= uj)) {
+            ++j;
+        } else {
+            anc[lo + i] = (int32_t)(base + (j < len ? j : jstar));
+            ++i;
+            if (i < ns)
+                uj = u_at(i);
         }
-        anc[i] = (int32_t)(base + (l < len ? l : jstar));
     }
     if (b == 0 && tid == 0) {
         scalars[SMC_S_RESAMPLED] = 1.0;
         scalars[SMC_S_LPRE] = scalars[SMC_S_L];
-        scalars[SMC_S_L] = log((double)n);
+        scalars[SMC_S_L] = log(nd);
         scalars[SMC_S_U] = SCHEME == SMC_RS_SYSTEMATIC ? U : 0.0;
     }
 }
@@ -474,15 +638,16 @@ __global__ __launch_bounds__(TPB) void mn_tile_sum_kernel(const double *__restri
         gtile[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(FIN_PASS_TPB) void mn_prefix_kernel(
-    const double *__restrict__ scalars, int32_t force, const double *__restrict__ gtile,
-    int64_t gtiles, double *__restrict__ gprefix)
+__global__ __launch_bounds__(FIN_TPB) void mn_prefix_kernel(const double *__restrict__ scalars,
+                                                            int32_t force,
+                                                            const double *__restrict__ gtile,
+                                                            int64_t gtiles,
+                                                            double *__restrict__ gprefix)
 {
-    __shared__ double sv[FIN_LDS];
-    __shared__ double red[FIN_PASS_TPB / WAVE];
+    __shared__ double red[FIN_NW];
     if (!(force != 0 || scalars[SMC_S_FLAG] != 0.0))
         return;
-    tile_offsets(gtiles, [&](int64_t b) { return gtile[b]; }, gprefix, sv, red);
+    tile_offsets(gtiles, [&](int64_t b) { return gtile[b]; }, gprefix, red);
 }
 
 __global__ __launch_bounds__(TPB) void mn_write_kernel(const double *__restrict__ scalars,
@@ -518,13 +683,13 @@ hipError_t launch_resample(Ctx &c, int32_t step, int32_t force)
     const dim3 grid((unsigned)c.ntiles);
     switch (c.cfg.scheme) {
     case SMC_RS_SYSTEMATIC:
-        hipLaunchKernelGGL(resample_kernel<SMC_RS_SYSTEMATIC>, grid, dim3(TPB), 0, c.stream,
+        hipLaunchKernelGGL(resample_merge_kernel<SMC_RS_SYSTEMATIC>, grid, dim3(TPB), 0, c.stream,
                            c.buf.log_weight, c.partials(), c.prefix(), c.n, c.ntiles,
                            c.buf.scalars, c.buf.ancestors, key, (uint32_t)step, p, force,
                            (const double *)nullptr, c.counters());
         break;
     case SMC_RS_STRATIFIED:
-        hipLaunchKernelGGL(resample_kernel<SMC_RS_STRATIFIED>, grid, dim3(TPB), 0, c.stream,
+        hipLaunchKernelGGL(resample_merge_kernel<SMC_RS_STRATIFIED>, grid, dim3(TPB), 0, c.stream,
                            c.buf.log_weight, c.partials(), c.prefix(), c.n, c.ntiles,
                            c.buf.scalars, c.buf.ancestors, key, (uint32_t)step, p, force,
                            (const double *)nullptr, c.counters());
@@ -533,13 +698,13 @@ hipError_t launch_resample(Ctx &c, int32_t step, int32_t force)
         const int64_t count = c.n + 1;
         hipLaunchKernelGGL(mn_tile_sum_kernel, dim3((unsigned)c.gtiles), dim3(TPB), 0, c.stream,
                            c.buf.scalars, force, count, key, (uint32_t)step, p, c.gtile());
-        hipLaunchKernelGGL(mn_prefix_kernel, dim3(1), dim3(FIN_PASS_TPB), 0, c.stream, c.buf.scalars,
+        hipLaunchKernelGGL(mn_prefix_kernel, dim3(1), dim3(FIN_TPB), 0, c.stream, c.buf.scalars,
                            force, c.gtile(), c.gtiles, c.gprefix());
         hipLaunchKernelGGL(mn_write_kernel, dim3((unsigned)c.gtiles), dim3(TPB), 0, c.stream,
                            c.buf.scalars, force, count, key, (uint32_t)step, p, c.gprefix(),
                            c.g());
-        hipLaunchKernelGGL(resample_kernel<SMC_RS_MULTINOMIAL>, grid, dim3(TPB), 0, c.stream,
-                           c.buf.log_weight, c.partials(), c.prefix(), c.n, c.ntiles,
+        hipLaunchKernelGGL(resample_merge_kernel<SMC_RS_MULTINOMIAL>, grid, dim3(TPB), 0,
+                           c.stream, c.buf.log_weight, c.partials(), c.prefix(), c.n, c.ntiles,
                            c.buf.scalars, c.buf.ancestors, key, (uint32_t)step, p, force,
                            (const double *)c.g(), c.counters());
     }
@@ -592,14 +757,14 @@ __global__ __launch_bounds__(TPB) void mon_partial_kernel(
     }
 }
 
-__global__ __launch_bounds__(FIN_PASS_TPB) void mon_final_kernel(const double *__restrict__ mon,
-                                                                 int64_t ntiles, MonDest md,
-                                                                 double *__restrict__ hist,
-                                                                 int64_t hist_len)
+__global__ __launch_bounds__(FIN_TPB) void mon_final_kernel(const double *__restrict__ mon,
+                                                            int64_t ntiles, MonDest md,
+                                                            double *__restrict__ hist,
+                                                            int64_t hist_len)
 {
-    __shared__ double red[FIN_PASS_TPB / WAVE];
+    __shared__ double red[FIN_NW];
     __shared__ double col[MON_STRIDE];
-    mon_combine(mon, ntiles, md, hist, hist_len, red, col);
+    mon_combine<FIN_TPB>(mon, ntiles, md, hist, hist_len, red, col);
 }
 
 hipError_t launch_monitor(Ctx &c, int32_t step, double *out_dev, int rows, bool gather_pending,
@@ -617,7 +782,7 @@ hipError_t launch_monitor(Ctx &c, int32_t step, double *out_dev, int rows, bool 
                            c.buf.ancestors, c.buf.scalars, (int)gather_pending,
                            (int)reset_pending, c.mon(), c.ntiles);
     const MonDest md = mon_dest(c, step, rows, out_dev);
-    hipLaunchKernelGGL(mon_final_kernel, dim3(1), dim3(FIN_PASS_TPB), 0, c.stream, c.mon(),
+    hipLaunchKernelGGL(mon_final_kernel, dim3(1), dim3(FIN_TPB), 0, c.stream, c.mon(),
                        c.ntiles, md, c.buf.history, c.buf.history_len);
     return hipGetLastError();
 }

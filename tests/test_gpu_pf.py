@@ -197,6 +197,7 @@ def test_unfused_reweight_matches_fused(lib):
     b = pkg.ParticleFilter(3000, y, seed=2)
     a.init()
     b.init()
+    L.smc_monitor(b.ctx, 0)
     for t in range(1, 10):
         a.step(t)
         m = L.smc_move_args()
