@@ -106,6 +106,8 @@ def _declare(L):
         "orc_gmm_reweight": (None, [_dp, _dp, _i64, _d, _i32]),
         "orc_gmm_block": (_i32, [ctypes.POINTER(GmmCfg), _u32, _i32, _i32, _d, _d, _dp, _i64,
                                  _dp, _dp, _dp, _dp, _ip]),
+        "orc_gmm_block_trace": (_i32, [ctypes.POINTER(GmmCfg), _u32, _i32, _i32, _d, _d, _dp,
+                                       _i64, _dp, _dp, _dp, _dp, _ip, _dp, _dp]),
         "orc_gmm_run": (_d, [ctypes.POINTER(GmmCfg), _dp, _i64, _i32, _dp, _dp, _dp, _dp, _dp]),
     }
     for name, (res, args) in list(sig.items()) + list(gmm_sig.items()):
@@ -373,6 +375,23 @@ def gmm_block(cfg, t, block, sweep, alpha, scale, y, pop, ll, lp, grad=None):
                         _d_ptr(pop), _d_ptr(ll), _d_ptr(lp),
                         None if grad is None else _d_ptr(grad), _i_ptr(acc))
     return pop, ll, lp, grad, acc
+
+
+def gmm_block_trace(cfg, t, block, sweep, alpha, scale, y, pop, ll, lp, grad=None):
+    """gmm_block that also returns log r and log u of every decision."""
+    y = _f64(y)
+    pop = _f64(pop).copy()
+    ll = _f64(ll).copy()
+    lp = _f64(lp).copy()
+    grad = None if grad is None else _f64(grad).copy()
+    acc = np.zeros(cfg.n, dtype=np.int32)
+    logr = np.zeros(cfg.n)
+    logu = np.zeros(cfg.n)
+    lib().orc_gmm_block_trace(ctypes.byref(cfg), t, block, sweep, alpha, scale, _d_ptr(y), y.size,
+                              _d_ptr(pop), _d_ptr(ll), _d_ptr(lp),
+                              None if grad is None else _d_ptr(grad), _i_ptr(acc), _d_ptr(logr),
+                              _d_ptr(logu))
+    return pop, ll, lp, grad, acc, logr, logu
 
 
 def gmm_run(cfg, y, alpha, scales):

@@ -247,9 +247,10 @@ static double tempered(double lp, double ll, double alpha)
  * for the random walk.  accepted[i] (may be NULL) receives 0/1.  Returns the
  * number of accepted proposals.
  */
-int32_t orc_gmm_block(const orc_gmm_cfg *c, uint32_t t, int32_t block, int32_t sweep,
-                      double alpha, double scale, const double *y, int64_t nd, double *pop,
-                      double *ll, double *lp, double *grad, int32_t *accepted)
+static int32_t gmm_block_impl(const orc_gmm_cfg *c, uint32_t t, int32_t block, int32_t sweep,
+                              double alpha, double scale, const double *y, int64_t nd,
+                              double *pop, double *ll, double *lp, double *grad,
+                              int32_t *accepted, double *logr_out, double *logu_out)
 {
     int K = c->K, D = 3 * K - 1;
     int64_t n = c->n;
@@ -313,6 +314,10 @@ int32_t orc_gmm_block(const orc_gmm_cfg *c, uint32_t t, int32_t block, int32_t s
                        c->problem, w);
         double logu = log(orc_u53(w[0], w[1]));
         int acc = logu <= logr;
+        if (logr_out)
+            logr_out[i] = logr;
+        if (logu_out)
+            logu_out[i] = logu;
         if (acc) {
             put_phi(pop, n, D, i, prop);
             ll[i] = llp;
@@ -325,6 +330,24 @@ int32_t orc_gmm_block(const orc_gmm_cfg *c, uint32_t t, int32_t block, int32_t s
             accepted[i] = acc;
     }
     return count;
+}
+
+int32_t orc_gmm_block(const orc_gmm_cfg *c, uint32_t t, int32_t block, int32_t sweep,
+                      double alpha, double scale, const double *y, int64_t nd, double *pop,
+                      double *ll, double *lp, double *grad, int32_t *accepted)
+{
+    return gmm_block_impl(c, t, block, sweep, alpha, scale, y, nd, pop, ll, lp, grad, accepted,
+                          NULL, NULL);
+}
+
+/* Same, also returning log r and log u of every particle's decision. */
+int32_t orc_gmm_block_trace(const orc_gmm_cfg *c, uint32_t t, int32_t block, int32_t sweep,
+                            double alpha, double scale, const double *y, int64_t nd, double *pop,
+                            double *ll, double *lp, double *grad, int32_t *accepted,
+                            double *logr_out, double *logu_out)
+{
+    return gmm_block_impl(c, t, block, sweep, alpha, scale, y, nd, pop, ll, lp, grad, accepted,
+                          logr_out, logu_out);
 }
 
 /*
@@ -410,8 +433,8 @@ double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
         int32_t acc[3] = {0, 0, 0};
         for (int s = 0; s < (c->sweeps > 0 ? c->sweeps : 1); ++s)
             for (int b = 0; b < 3; ++b)
-                acc[b] += orc_gmm_block(c, (uint32_t)t, b, s, a, scales[3 * t + b], y, nd, pop,
-                                        ll, lp, grad, NULL);
+                acc[b] += gmm_block_impl(c, (uint32_t)t, b, s, a, scales[3 * t + b], y, nd, pop,
+                                         ll, lp, grad, NULL, NULL, NULL);
         if (hist) {
             double *h = hist + 9 * (int64_t)t;
             h[0] = nz[2];

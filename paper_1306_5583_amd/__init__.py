@@ -8,6 +8,6 @@ from ._lib import SmcError
 
 _lib.load()
 
-from .sampler import ParticleFilter  # noqa: E402
+from .sampler import GmmSampler, ParticleFilter, mala_scales, rw_scales  # noqa: E402
 
-__all__ = ["ParticleFilter", "SmcError"]
+__all__ = ["ParticleFilter", "GmmSampler", "rw_scales", "mala_scales", "SmcError"]

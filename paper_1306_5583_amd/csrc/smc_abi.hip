@@ -391,6 +391,14 @@ smc_status smc_reweight(smc_ctx *ctx, int32_t step, const smc_reweight_args *arg
     } else {
         if (!isfinite(args->dalpha))
             return fail(c, SMC_ERR_INVALID_ARG, "dalpha must be finite");
+        if (c.armed_gather) {
+            // the cached log-likelihood must be read at the resampled state
+            e = launch_gather(c);
+            if (e != hipSuccess)
+                return hip_status(c, e, "smc_reweight");
+            c.cur ^= 1;
+            c.armed_gather = false;
+        }
         e = launch_gmm_reweight(c, args->dalpha, c.armed_lw);
     }
     c.armed_lw = false;

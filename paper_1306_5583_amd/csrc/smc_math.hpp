@@ -6,6 +6,9 @@
 //              log m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...)  (Abramowitz &
 //              Stegun 4.1.27), |s| <= 0.1716 so 12 terms reach 1e-19;
 //              log x = e ln2 + log m with ln2 split in a high and a low part.
+//  exp_d(x):   x = k ln2 + r with k = rint(x / ln2) and |r| <= ln2/2 (Cody &
+//              Waite reduction with ln2 in two parts), e^r by its Taylor series
+//              to degree 13 (truncation below 5e-18), then scaled by 2^k.
 //  sincospi_d: sin(pi x), cos(pi x) by exact reduction to r = x - n/2,
 //              |r| <= 1/4, and the Taylor series of sin(pi r), cos(pi r)
 //              (truncation below 2e-22 for |pi r| <= pi/4), then the
@@ -35,6 +38,11 @@ constexpr double ipow(double x, int k) { return k == 0 ? 1.0 : x * ipow(x, k - 1
 constexpr double sin_c(int k) { return (k % 2 ? -1.0 : 1.0) * ipow(kPi, 2 * k + 1) / fact(2 * k + 1); }
 // cos(pi r) = sum_k C_k r^(2k),  C_k = (-1)^k pi^(2k) / (2k)!
 constexpr double cos_c(int k) { return (k % 2 ? -1.0 : 1.0) * ipow(kPi, 2 * k) / fact(2 * k); }
+constexpr double exp_c(int k) { return 1.0 / fact(k); }
+constexpr double kExpC[14] = {exp_c(0), exp_c(1), exp_c(2),  exp_c(3),  exp_c(4),
+                              exp_c(5), exp_c(6), exp_c(7),  exp_c(8),  exp_c(9),
+                              exp_c(10), exp_c(11), exp_c(12), exp_c(13)};
+constexpr double kLog2e = 1.4426950408889634073599246810019;
 constexpr double kSinC[10] = {sin_c(0), sin_c(1), sin_c(2), sin_c(3), sin_c(4),
                               sin_c(5), sin_c(6), sin_c(7), sin_c(8), sin_c(9)};
 constexpr double kCosC[10] = {cos_c(0), cos_c(1), cos_c(2), cos_c(3), cos_c(4),
@@ -66,6 +74,23 @@ __host__ __device__ inline double log_d(double x)
     r = (x < 0.0 || x != x) ? __builtin_nan("") : r;
     r = (x == INFINITY) ? INFINITY : r;
     return r;
+}
+
+// Exponential; exp(-inf) = 0, exp(x < -745.2) = 0 (through gradual
+// underflow), exp(x > 709.8) = inf, NaN propagates.
+__host__ __device__ inline double exp_d(double x)
+{
+    const double xc = fmin(fmax(x, -1100.0), 1100.0);
+    const double k = rint(xc * detail::kLog2e);
+    double r = fma(-k, detail::kLn2Hi, xc);
+    r = fma(-k, detail::kLn2Lo, r);
+    double p = detail::kExpC[13];
+#pragma unroll
+    for (int j = 12; j >= 0; --j)
+        p = fma(p, r, detail::kExpC[j]);
+    double v = ldexp(p, (int)k);
+    v = (x != x) ? x : v;
+    return v;
 }
 
 // sin(pi x) and cos(pi x) for |x| < 2^50.

@@ -48,6 +48,23 @@ int main()
         if (std::fabs((double)cr) > 1e-3)
             e_cos = std::fmax(e_cos, ulp_err(c, cr));
     }
+    double e_exp = 0;
+    for (int i = 0; i < 2000000; ++i) {
+        const double x = -745.0 * U(g) + (i % 7 == 0 ? 709.0 * U(g) : 0.0);
+        const long double ref = expl((long double)x);
+        if ((double)ref < 2.3e-308)   // compare normal results in ulp
+            continue;
+        e_exp = std::fmax(e_exp, ulp_err(smc::exp_d(x), ref));
+    }
+    for (int i = 0; i < 200000; ++i) {
+        const double x = (U(g) - 0.5) * 1e-3;
+        e_exp = std::fmax(e_exp, ulp_err(smc::exp_d(x), expl((long double)x)));
+    }
+    const bool exp_special = smc::exp_d(-INFINITY) == 0.0 && smc::exp_d(0.0) == 1.0 &&
+                             std::isinf(smc::exp_d(710.0)) && smc::exp_d(-800.0) == 0.0 &&
+                             std::isnan(smc::exp_d(NAN)) &&
+                             std::fabs(smc::exp_d(-740.0) - std::exp(-740.0)) <= 1e-320;
+    std::printf("exp_ulp %.3f\nexp_special %d\n", e_exp, (int)exp_special);
     const bool special = std::isinf(smc::log_d(0.0)) && smc::log_d(0.0) < 0 &&
                          std::isnan(smc::log_d(-1.0)) && std::isinf(smc::log_d(INFINITY)) &&
                          smc::log_d(1.0) == 0.0 && std::isnan(smc::log_d(NAN));

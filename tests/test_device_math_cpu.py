@@ -25,3 +25,5 @@ def test_math_functions_within_few_ulp(tmp_path):
     assert float(vals["cospi_ulp"]) < 4.0
     assert float(vals["sincospi_abs"]) < 5e-16
     assert vals["special"] == "1"
+    assert float(vals["exp_ulp"]) < 4.0
+    assert vals["exp_special"] == "1"

@@ -1,0 +1,231 @@
+"""GPU parity of the tempered Gaussian-mixture sampler (Section 5.2) against
+the oracle, through the C ABI: prior draws and the first likelihood, the
+reweighting by the tempering increment, normalisation and resampling, the
+three Metropolis blocks (random walk and MALA) in lock-step with every
+decision checked against the oracle's log r and log u, the adjoint entry
+point, a whole run end to end, and prior invariance at tempering 0."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import assert_ancestors, assert_close_l1, decision_matches
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_5583_amd as pkg
+    from paper_1306_5583_amd import _lib
+    _lib.load()
+    return pkg, _lib
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _state(s, K):
+    """(phi[D][n], ll[n], lp[n], grad or None) from the GPU state rows."""
+    D = 3 * K - 1
+    x = s.state().cpu().numpy()
+    grad = x[D + 2:2 * D + 2] if x.shape[0] > D + 2 else None
+    return x[:D].copy(), x[D].copy(), x[D + 1].copy(), None if grad is None else grad.copy()
+
+
+def _mass(ll, alpha=1.0):
+    # L1 mass of the log-likelihood summands: every point's log density is
+    # negative for these data, so sum_k |L_k| = |l|
+    return np.abs(ll) * max(alpha, 1.0) + 50.0
+
+
+@pytest.mark.parametrize("K,move", [(1, "rw"), (4, "rw"), (3, "mala"), (6, "mala")])
+def test_init_parity(lib, orc, K, move):
+    pkg, L = lib
+    n, nd = 3001, 257
+    y = synth.gmm_data(nd, np.linspace(-3, 3, K), 2.0, np.ones(K), 5)
+    s = pkg.GmmSampler(n, y, K, 10, seed=7, move=move)
+    s.init()
+    torch.cuda.synchronize()
+    phi, ll, lp, grad = _state(s, K)
+    ocfg = orc.gmm_cfg(n, 7, K, move=move)
+    pop_o, ll_o, lp_o = orc.gmm_init(ocfg, y)
+    assert_close_l1(phi, pop_o, np.abs(pop_o) + 1, 1e-12, "phi")
+    assert_close_l1(ll, ll_o, _mass(ll_o), 1e-12, "loglik")
+    assert_close_l1(lp, lp_o, np.abs(lp_o) + 10, 1e-12, "logprior")
+    if move == "mala":
+        for i in range(0, n, 97):
+            _, g = orc.gmm_loglik(pop_o[:, i], K, y, grad=True)
+            assert_close_l1(grad[:, i], g, np.abs(g) + 2 * nd, 1e-12, "grad %d" % i)
+    assert np.all(s.log_weight.cpu().numpy() == 0.0)
+    s.check()
+
+
+def _lockstep_gmm(lib, orc, n, K, nd, T, move, seed=3, threshold=0.5, sweeps=1, power=4.0,
+                  alpha_zero=False):
+    pkg, L = lib
+    _say("gmm lockstep n=%d K=%d nd=%d T=%d move=%s" % (n, K, nd, T, move))
+    y, _ = synth.gmm_data_spaced(nd, K, 11)
+    s = pkg.GmmSampler(n, y, K, T, seed=seed, move=move, threshold=threshold, sweeps=sweeps)
+    ocfg = orc.gmm_cfg(n, seed, K, move=move, threshold=threshold, sweeps=sweeps)
+    alphas = np.zeros(T + 1) if alpha_zero else synth.prior_tempering(T, power)
+    s.init()
+    torch.cuda.synchronize()
+    a_prev = 0.0
+    flips = 0
+    total_decisions = 0
+    for t in range(1, T + 1):
+        a = float(alphas[t])
+        dalpha = 0.0 if a == 0.0 else a - a_prev
+        a_prev = a
+        phi, ll, lp, grad = _state(s, K)
+        lw_in = s.log_weight.cpu().numpy().copy()
+        sc = s.scalars_host()
+        reset = sc[L.SMC_S_RESAMPLED] != 0.0 and t > 1
+        # reweight + normalise
+        s._rargs.dalpha = dalpha
+        L.smc_reweight(s.ctx, t, s._rargs)
+        L.smc_ess(s.ctx, t)
+        torch.cuda.synchronize()
+        lw = s.log_weight.cpu().numpy()
+        lw_o = orc.gmm_reweight(lw_in, ll, dalpha, reset)
+        assert_close_l1(lw, lw_o, np.abs(lw_in) + np.abs(dalpha * ll) + 1, 1e-12, "lw t=%d" % t)
+        sc = s.scalars_host()
+        Lo, _, esso = orc.normalise(lw)
+        assert abs(sc[L.SMC_S_L] - Lo) <= 1e-12 * max(1.0, abs(Lo))
+        assert abs(sc[L.SMC_S_ESS] - esso) <= 1e-12 * esso
+        assert decision_matches(sc[L.SMC_S_FLAG], orc.resample_flag(esso, n, threshold), esso,
+                                threshold * n)
+        L.smc_resample(s.ctx, t)
+        torch.cuda.synchronize()
+        sc = s.scalars_host()
+        resampled = sc[L.SMC_S_RESAMPLED] != 0.0
+        anc = s.ancestors.cpu().numpy().astype(np.int64)
+        if resampled:
+            anc_o, S_o, u_o = orc.resample("systematic", seed, t, lw)
+            flips += assert_ancestors(anc, anc_o, S_o, u_o, what="anc t=%d" % t)
+            phi, ll, lp = phi[:, anc], ll[anc], lp[anc]
+            grad = None if grad is None else grad[:, anc]
+        # the three blocks (one smc_move call), then the oracle replays them
+        scales = pkg.rw_scales(a) if move == "rw" else pkg.mala_scales(a)
+        m = L.smc_move_args()
+        m.alpha = a
+        for q in range(3):
+            m.scale[q] = scales[q]
+        L.smc_move(s.ctx, t, m)
+        torch.cuda.synchronize()
+        phi_g, ll_g, lp_g, grad_g = _state(s, K)
+        # oracle replays the blocks from the GPU's input, carrying the GPU's
+        # decisions forward where they fall in the boundary window
+        po, lo_, pro, go = phi, ll, lp, grad
+        margin = np.full(n, np.inf)
+        for sweep in range(sweeps):
+            for b in range(3):
+                if b == 2 and K == 1:
+                    continue
+                po, lo_, pro, go, acc, logr, logu = orc.gmm_block_trace(
+                    ocfg, t, b, sweep, a, scales[b], y, po, lo_, pro, go)
+                margin = np.minimum(margin, np.abs(logr - logu) / np.maximum(1.0, _mass(lo_, a)))
+                total_decisions += n
+        # compare final states; mismatching particles must be explained by a
+        # decision within the boundary window of some block
+        scale_phi = np.abs(po) + np.abs(phi) + 1.0
+        bad = np.zeros(n, dtype=bool)
+        err = np.abs(phi_g - po) > 1e-12 * np.maximum(1.0, scale_phi)
+        bad |= err.any(axis=0)
+        bad |= np.abs(ll_g - lo_) > 1e-12 * _mass(lo_, a)
+        if bad.any():
+            idx = np.flatnonzero(bad)
+            # a differing particle must have met a decision within the window
+            assert np.all(margin[idx] <= 1e-11), ("t=%d: particles %s differ, margins %s"
+                                                  % (t, idx[:5], margin[idx][:5]))
+            flips += idx.size
+        assert_close_l1(lp_g[~bad], pro[~bad], np.abs(pro[~bad]) + 10, 1e-12, "lp t=%d" % t)
+        if go is not None:
+            for i in np.flatnonzero(~bad)[:: max(1, n // 50)]:
+                assert_close_l1(grad_g[:, i], go[:, i], np.abs(go[:, i]) + 2 * nd, 1e-12, "grad")
+        L.smc_monitor(s.ctx, t)
+    s.check()
+    _say("  flips %d of %d decisions" % (flips, total_decisions))
+    return s
+
+
+@pytest.mark.parametrize("n,K,nd,move", [(2048, 4, 200, "rw"), (3000, 1, 100, "rw"),
+                                         (4096, 3, 150, "mala"), (5000, 6, 300, "mala")])
+def test_lockstep(lib, orc, n, K, nd, move):
+    _lockstep_gmm(lib, orc, n, K, nd, 12, move)
+
+
+def test_lockstep_two_sweeps(lib, orc):
+    _lockstep_gmm(lib, orc, 2500, 4, 120, 6, "rw", sweeps=2)
+
+
+def test_end_to_end_small(lib, orc):
+    pkg, L = lib
+    K, n, nd, T = 4, 4096, 100, 20
+    y = synth.gmm_data_four_components(nd, 8)
+    alphas = synth.prior_tempering(T, 4.0)
+    s = pkg.GmmSampler(n, y, K, T, seed=5)
+    logz_g = s.run(alphas)
+    hist = s.history_host()
+    scales = np.array([pkg.rw_scales(a) for a in alphas])
+    logz_o, hist_o, pop_o, lwf_o = orc.gmm_run(orc.gmm_cfg(n, 5, K), y, alphas, scales)
+    assert abs(logz_g - logz_o) <= 1e-9 * max(1.0, np.abs(hist_o[:, 2]).sum()) + 1e-9
+    assert np.array_equal(hist[1:, L.SMC_H_FLAG], hist_o[1:, 1])
+    acc_g = hist[1:, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3]
+    assert np.all(np.abs(acc_g - hist_o[1:, 5:8]) <= 2)
+    s.check()
+
+
+def test_alpha_zero_prior_invariance(lib):
+    pkg, L = lib
+    K, n, T = 4, 1 << 16, 15
+    y = synth.gmm_data_four_components(50, 3)
+    s = pkg.GmmSampler(n, y, K, T, seed=9)
+    logz = s.run(np.zeros(T + 1))
+    assert logz == 0.0
+    hist = s.history_host()
+    assert np.all(hist[1:, L.SMC_H_FLAG] == 0)
+    assert np.allclose(hist[1:, L.SMC_H_ESS], n, rtol=1e-12)
+    phi = s.state().cpu().numpy()[:3 * K - 1]
+    mu, eta, z = phi[:K], phi[K:2 * K], phi[2 * K:]
+    assert np.all(np.abs(mu.mean(axis=1)) < 5 * 10 / math.sqrt(n))
+    assert np.all(np.abs(mu.var(axis=1) / 100 - 1) < 5 * math.sqrt(2 / n))
+    lam = np.exp(eta)
+    assert np.all(np.abs(lam.mean(axis=1) - 1) < 5 / math.sqrt(n))
+    zz = np.vstack([z, np.zeros((1, n))])
+    w = np.exp(zz - zz.max(axis=0)) / np.exp(zz - zz.max(axis=0)).sum(axis=0)
+    assert np.all(np.abs(w.mean(axis=1) - 0.25) < 5 * math.sqrt(0.0375 / n))
+
+
+@pytest.mark.parametrize("K", [1, 2, 6, 8])
+def test_loglik_grad_entry(lib, orc, K):
+    pkg, L = lib
+    n, nd = 64, 10000
+    y, _ = synth.gmm_data_spaced(nd, max(K, 1), 1309)
+    rng = np.random.default_rng(K)
+    mu = rng.normal(0, 3, (K, n))
+    eta = rng.normal(0, 0.5, (K, n))
+    z = rng.normal(0, 0.5, (max(K - 1, 1), n))
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    mu_d, eta_d, z_d, y_d = dev(mu), dev(eta), dev(z), dev(y)
+    ll = torch.zeros(n, dtype=torch.float64, device="cuda")
+    g = torch.zeros((3 * K - 1, n), dtype=torch.float64, device="cuda")
+    L.smc_gmm_loglik_grad(mu_d.data_ptr(), eta_d.data_ptr(), z_d.data_ptr(), n, K,
+                          y_d.data_ptr(), nd, ll.data_ptr(), g.data_ptr(),
+                          torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    ll, g = ll.cpu().numpy(), g.cpu().numpy()
+    for i in range(n):
+        phi = np.concatenate([mu[:, i], eta[:, i], z[:K - 1, i]])
+        v, gr = orc.gmm_loglik(phi, K, y, grad=True)
+        assert_close_l1(ll[i], v, abs(v) + 50, 1e-12, "ll")
+        assert_close_l1(g[:, i], gr, np.abs(gr) + 2 * nd, 1e-12, "grad")
