@@ -10,4 +10,7 @@ _lib.load()
 
 from .sampler import GmmSampler, ParticleFilter, mala_scales, rw_scales  # noqa: E402
 
-__all__ = ["ParticleFilter", "GmmSampler", "rw_scales", "mala_scales", "SmcError"]
+from .autograd import GmmLogLik, gmm_loglik  # noqa: E402
+
+__all__ = ["ParticleFilter", "GmmSampler", "GmmLogLik", "gmm_loglik", "rw_scales",
+           "mala_scales", "SmcError"]
