@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsmc.so")
-SOURCES = ["smc_abi.hip", "smc_core.hip", "smc_pf.hip", "smc_gmm.hip"]
+SOURCES = ["smc_abi.hip", "smc_core.hip", "smc_pf.hip", "smc_gmm.hip", "smc_gmm_ka.hip",
+           "smc_gmm_kb.hip", "smc_gmm_kc.hip", "smc_gmm_kd.hip"]
 ARCH = "gfx950"
 
 
@@ -27,7 +28,7 @@ def compile_flags():
             "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every HIP source to an object, then link the shared library."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)

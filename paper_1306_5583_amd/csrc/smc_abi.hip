@@ -51,6 +51,65 @@ Workspace plan_workspace(const smc_config &cfg)
     return w;
 }
 
+static Prob prob_from(const smc_config &cfg, const smc_buffers &buf, const Workspace &ws,
+                      void *s0, void *s1)
+{
+    Prob P{};
+    P.kind = cfg.model;
+    P.move_kind = cfg.move_kind;
+    P.n = cfg.n;
+    P.n_data = cfg.model == SMC_MODEL_CV_TRACK ? (int64_t)cfg.n_obs : cfg.n_data;
+    P.ntiles = ceil_div(cfg.n, TILE);
+    P.key = make_key(cfg.seed);
+    P.problem_id = cfg.problem_id;
+    P.K = cfg.K;
+    P.scheme = cfg.scheme;
+    P.threshold = cfg.threshold;
+    P.mv = Motion{cfg.dt, cfg.sd_pos, cfg.sd_vel};
+    if (cfg.model == SMC_MODEL_CV_TRACK) {
+        const double sc = cfg.obs_scale;
+        P.obs.inv_s = 1.0 / sc;
+        if (isinf(cfg.obs_nu)) {
+            P.obs.gaussian = 1;
+            P.obs.c = -0.5 * log(2.0 * M_PI * sc * sc);
+            P.obs.half_nu1 = 0.0;
+            P.obs.inv_nu = 0.0;
+        } else {
+            const double nu = cfg.obs_nu;
+            P.obs.gaussian = 0;
+            P.obs.half_nu1 = 0.5 * (nu + 1.0);
+            P.obs.inv_nu = 1.0 / nu;
+            P.obs.c = cfg.paper_compatible_loglik ? 0.0
+                                                  : lgamma(0.5 * (nu + 1.0)) - lgamma(0.5 * nu) -
+                                                        0.5 * log(nu * M_PI) - log(sc);
+        }
+    }
+    for (int k = 0; k < 4; ++k)
+        P.init_sd[k] = cfg.init_sd[k];
+    if (cfg.model == SMC_MODEL_GMM_TEMPERED) {
+        P.prior = GmmPrior{cfg.prior_mu_mean, 1.0 / (2.0 * cfg.prior_mu_sd * cfg.prior_mu_sd),
+                           cfg.prior_gamma_shape, cfg.prior_gamma_rate, cfg.prior_dir_rho};
+        P.mu_sd = cfg.prior_mu_sd;
+    }
+    P.state[0] = s0;
+    P.state[1] = s1;
+    P.lw = buf.log_weight;
+    P.anc = buf.ancestors;
+    P.data = buf.data;
+    P.hist = buf.history;
+    P.hist_len = buf.history ? buf.history_len : 0;
+    P.scalars = buf.scalars;
+    char *w = static_cast<char *>(buf.workspace);
+    P.partials = reinterpret_cast<TilePartial *>(w + ws.partials);
+    P.prefix = reinterpret_cast<double *>(w + ws.prefix);
+    P.mon = reinterpret_cast<double *>(w + ws.mon);
+    P.counters = reinterpret_cast<int32_t *>(w + ws.counters);
+    P.sched = nullptr;
+    return P;
+}
+
+Prob make_prob(const Ctx &c) { return prob_from(c.cfg, c.buf, c.ws, c.state_ptr(), c.other_ptr()); }
+
 static smc_status validate_config(const smc_config *cfg, std::string &err)
 {
     if (!cfg) {
@@ -271,21 +330,6 @@ smc_status smc_create(const smc_config *cfg, const smc_buffers *buf, void *hip_s
     c.gtiles = ceil_div(c.n + 1, TILE);
     c.state_rows = state_rows_of(*cfg);
     c.elem_bytes = (cfg->model == SMC_MODEL_CV_TRACK && cfg->precision == SMC_F32_STATE) ? 4 : 8;
-    if (cfg->model == SMC_MODEL_CV_TRACK) {
-        const double s_ = cfg->obs_scale;
-        c.obs_inv_scale = 1.0 / s_;
-        if (isinf(cfg->obs_nu)) {
-            c.obs_const = -0.5 * log(2.0 * M_PI * s_ * s_);
-            c.obs_half_nu1 = 0.0;
-        } else {
-            const double nu = cfg->obs_nu;
-            c.obs_half_nu1 = 0.5 * (nu + 1.0);
-            c.obs_const = cfg->paper_compatible_loglik
-                              ? 0.0
-                              : lgamma(0.5 * (nu + 1.0)) - lgamma(0.5 * nu) -
-                                    0.5 * log(nu * M_PI) - log(s_);
-        }
-    }
     *out = h;
     return SMC_OK;
 }

@@ -180,14 +180,19 @@ __device__ void mon_combine(const double *__restrict__ mon, int64_t ntiles, cons
 
 constexpr int FIN_MON_ROWS = 4;  // rows a move can carry (the tracking state)
 
-__global__ __launch_bounds__(FIN_TPB) void finalize_kernel(
-    const TilePartial *__restrict__ part, int64_t ntiles, int64_t n, double threshold,
-    double *__restrict__ prefix, double *__restrict__ scalars, double *__restrict__ hist,
-    int64_t hist_len, int32_t step, int32_t *__restrict__ counters,
-    const double *__restrict__ mon, MonDest md)
+__device__ __forceinline__ void finalize_block(const Prob &P, int32_t step, const MonDest &md)
 {
     __shared__ double red[FIN_NW * (FIN_MON_ROWS + 2)];
     __shared__ double col[MON_STRIDE];
+    const TilePartial *__restrict__ part = P.partials;
+    const int64_t ntiles = P.ntiles, n = P.n;
+    const double threshold = P.threshold;
+    double *__restrict__ prefix = P.prefix;
+    double *__restrict__ scalars = P.scalars;
+    double *__restrict__ hist = P.hist;
+    const int64_t hist_len = P.hist_len;
+    int32_t *__restrict__ counters = P.counters;
+    const double *__restrict__ mon = P.mon;
     const int tid = threadIdx.x;
     double M, S1, S2;
     if (ntiles <= FIN_PASS) {
@@ -298,6 +303,69 @@ __global__ __launch_bounds__(FIN_TPB) void finalize_kernel(
     }
 }
 
+__global__ __launch_bounds__(FIN_TPB) void finalize_kernel(Prob P, int32_t step, MonDest md)
+{
+    finalize_block(P, step, md);
+}
+
+// Batched normalisation: one workgroup per problem; tracking problems also
+// complete the monitor of the previous step carried by the batched move.
+__global__ __launch_bounds__(FIN_TPB) void finalize_batch_kernel(const Prob *__restrict__ probs,
+                                                                 const int32_t *__restrict__ step)
+{
+    const Prob &P = probs[blockIdx.x];
+    const int32_t t = *step;
+    MonDest md;
+    md.out = nullptr;
+    md.rows = FIN_MON_ROWS;
+    md.hist_col = SMC_H_MON;
+    md.hist_ncols = FIN_MON_ROWS;
+    md.step = (P.kind == SMC_MODEL_CV_TRACK && t >= 1) ? t - 1 : -1;
+    finalize_block(P, t, md);
+}
+
+hipError_t launch_finalize_batch(const Prob *probs, int32_t nprob, const int32_t *step,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_batch_kernel, dim3((unsigned)nprob), dim3(FIN_TPB), 0, s, probs,
+                       step);
+    return hipGetLastError();
+}
+
+__global__ void reset_scalars_batch_kernel(const Prob *__restrict__ probs)
+{
+    const Prob &P = probs[blockIdx.x];
+    const int t = threadIdx.x;
+    if (t < SMC_SCALARS_LEN)
+        P.scalars[t] = 0.0;
+    if (t < 16)
+        P.counters[t] = 0;
+    __syncthreads();
+    if (t == 0) {
+        P.scalars[SMC_S_L] = log((double)P.n);
+        P.scalars[SMC_S_L2] = log((double)P.n);
+        P.scalars[SMC_S_ESS] = (double)P.n;
+    }
+}
+
+__global__ void set_step_kernel(int32_t *step, int32_t value, int32_t add)
+{
+    if (threadIdx.x == 0)
+        *step = add ? *step + value : value;
+}
+
+hipError_t launch_reset_scalars_batch(const Prob *probs, int32_t nprob, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_scalars_batch_kernel, dim3((unsigned)nprob), dim3(64), 0, s, probs);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_step(int32_t *step, int32_t value, int32_t add, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, s, step, value, add);
+    return hipGetLastError();
+}
+
 static MonDest mon_dest(const Ctx &c, int32_t step, int rows, double *out)
 {
     MonDest d;
@@ -319,9 +387,8 @@ hipError_t launch_finalize(Ctx &c, int32_t step)
     MonDest md = mon_dest(c, c.mon_pending_step, c.mon_pending_rows, c.mon_pending_out);
     if (c.mon_pending_step < 0)
         md.step = -1;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_TPB), 0, c.stream, c.partials(),
-                       c.ntiles, c.n, c.cfg.threshold, c.prefix(), c.buf.scalars, c.buf.history,
-                       c.buf.history_len, step, c.counters(), c.mon(), md);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_TPB), 0, c.stream, make_prob(c), step,
+                       md);
     c.mon_pending_step = -1;
     return hipGetLastError();
 }
@@ -498,12 +565,18 @@ __device__ __forceinline__ TileCdf tile_cdf(const double *__restrict__ lw, int64
 constexpr int RS_UCAP = 2048;
 
 template <int SCHEME>
-__global__ __launch_bounds__(TPB) void resample_merge_kernel(
-    const double *__restrict__ lw, const TilePartial *__restrict__ part,
-    const double *__restrict__ prefix, int64_t n, int64_t ntiles, double *__restrict__ scalars,
-    int32_t *__restrict__ anc, Key key, uint32_t t, uint32_t p, int32_t force,
-    const double *__restrict__ G, int32_t *__restrict__ counters)
+__device__ __forceinline__ void resample_tile(const Prob &P, int64_t b, uint32_t t, int32_t force,
+                                              const double *__restrict__ G)
 {
+    const double *__restrict__ lw = P.lw;
+    const TilePartial *__restrict__ part = P.partials;
+    const double *__restrict__ prefix = P.prefix;
+    const int64_t n = P.n, ntiles = P.ntiles;
+    double *__restrict__ scalars = P.scalars;
+    int32_t *__restrict__ anc = P.anc;
+    const Key key = P.key;
+    const uint32_t p = P.problem_id;
+    int32_t *__restrict__ counters = P.counters;
     __shared__ double sS[TILE];
     __shared__ double sU[RS_UCAP];
     __shared__ double red[NWAVES];
@@ -515,11 +588,10 @@ __global__ __launch_bounds__(TPB) void resample_merge_kernel(
     const uint4 wU = draw(key, 0, t, TAG_RESAMPLE, 0, p);
     const double U = u53(wU.x, wU.y);
     if (!go) {
-        if (blockIdx.x == 0 && tid == 0)
+        if (b == 0 && tid == 0)
             scalars[SMC_S_RESAMPLED] = 0.0;
         return;
     }
-    const int64_t b = blockIdx.x;
     const int64_t base = b * TILE;
     const int len = (int)min((int64_t)TILE, n - base);
     const double M = scalars[SMC_S_M];
@@ -609,6 +681,22 @@ __global__ __launch_bounds__(TPB) void resample_merge_kernel(
     }
 }
 
+template <int SCHEME>
+__global__ __launch_bounds__(TPB) void resample_merge_kernel(Prob P, uint32_t t, int32_t force,
+                                                             const double *__restrict__ G)
+{
+    resample_tile<SCHEME>(P, blockIdx.x, t, force, G);
+}
+
+// Batched systematic resampling over the tiles of many problems.
+__global__ __launch_bounds__(TPB) void resample_batch_kernel(const Prob *__restrict__ probs,
+                                                             const int2 *__restrict__ map,
+                                                             const int32_t *__restrict__ step)
+{
+    const int2 pm = map[blockIdx.x];
+    resample_tile<SMC_RS_SYSTEMATIC>(probs[pm.x], pm.y, (uint32_t)*step, 0, nullptr);
+}
+
 // --- multinomial: cumulative sums G of N+1 exponentials -------------------
 
 __device__ __forceinline__ double mn_exp(Key key, int64_t k, uint32_t t, uint32_t p)
@@ -678,21 +766,18 @@ __global__ __launch_bounds__(TPB) void mn_write_kernel(const double *__restrict_
 
 hipError_t launch_resample(Ctx &c, int32_t step, int32_t force)
 {
+    const Prob P = make_prob(c);
     const Key key = make_key(c.cfg.seed);
     const uint32_t p = c.cfg.problem_id;
     const dim3 grid((unsigned)c.ntiles);
     switch (c.cfg.scheme) {
     case SMC_RS_SYSTEMATIC:
         hipLaunchKernelGGL(resample_merge_kernel<SMC_RS_SYSTEMATIC>, grid, dim3(TPB), 0, c.stream,
-                           c.buf.log_weight, c.partials(), c.prefix(), c.n, c.ntiles,
-                           c.buf.scalars, c.buf.ancestors, key, (uint32_t)step, p, force,
-                           (const double *)nullptr, c.counters());
+                           P, (uint32_t)step, force, (const double *)nullptr);
         break;
     case SMC_RS_STRATIFIED:
         hipLaunchKernelGGL(resample_merge_kernel<SMC_RS_STRATIFIED>, grid, dim3(TPB), 0, c.stream,
-                           c.buf.log_weight, c.partials(), c.prefix(), c.n, c.ntiles,
-                           c.buf.scalars, c.buf.ancestors, key, (uint32_t)step, p, force,
-                           (const double *)nullptr, c.counters());
+                           P, (uint32_t)step, force, (const double *)nullptr);
         break;
     default: {
         const int64_t count = c.n + 1;
@@ -704,11 +789,19 @@ hipError_t launch_resample(Ctx &c, int32_t step, int32_t force)
                            c.buf.scalars, force, count, key, (uint32_t)step, p, c.gprefix(),
                            c.g());
         hipLaunchKernelGGL(resample_merge_kernel<SMC_RS_MULTINOMIAL>, grid, dim3(TPB), 0,
-                           c.stream, c.buf.log_weight, c.partials(), c.prefix(), c.n, c.ntiles,
-                           c.buf.scalars, c.buf.ancestors, key, (uint32_t)step, p, force,
-                           (const double *)c.g(), c.counters());
+                           c.stream, P, (uint32_t)step, force, (const double *)c.g());
     }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_resample_batch(const Prob *probs, const int2 *map, int64_t tiles,
+                                 const int32_t *step, hipStream_t s)
+{
+    if (tiles == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(resample_batch_kernel, dim3((unsigned)tiles), dim3(TPB), 0, s, probs, map,
+                       step);
     return hipGetLastError();
 }
 

@@ -27,6 +27,68 @@ struct Workspace {
 
 constexpr int MON_STRIDE = 32;  // monitor partial: sum w, then up to 31 weighted rows
 
+// Observation log-density of the tracking model for both coordinates:
+// Student-t with nu degrees of freedom and scale s per coordinate,
+//   c - (nu+1)/2 log1p(((y-pos)/s)^2 / nu),
+// or Gaussian c - ((y-pos)/s)^2 / 2 when gaussian != 0.  The two independent
+// coordinates combine into one logarithm: log1p(a) + log1p(b) =
+// log((1 + a)(1 + b)).
+struct ObsModel {
+    double c, half_nu1, inv_nu, inv_s;
+    int gaussian;
+    __device__ __forceinline__ double operator()(double px, double yx, double py, double yy) const
+    {
+        const double rx = (yx - px) * inv_s;
+        const double ry = (yy - py) * inv_s;
+        if (gaussian)
+            return (c + c) - 0.5 * (rx * rx + ry * ry);
+        const double q = fma(rx * rx, inv_nu, 1.0) * fma(ry * ry, inv_nu, 1.0);
+        return (c + c) - half_nu1 * log_d(q);
+    }
+};
+
+struct Motion {
+    double dt, sd_pos, sd_vel;
+};
+
+struct GmmPrior {
+    double mu_mean, inv_2var, shape, rate, rho;
+};
+
+// Everything a kernel needs to know about one problem (one filter or one
+// sampler): sizes, model constants and device pointers.  Passed by value to
+// the single-problem kernels and read from a device table by the batched
+// ones, so both run the same tile code.
+struct Prob {
+    int32_t kind;       // smc_model
+    int32_t move_kind;  // GMM: smc_move_kind
+    int64_t n;          // particles
+    int64_t n_data;     // GMM data points / CV observation rows
+    int64_t ntiles;     // 1024-particle tiles
+    Key key;
+    uint32_t problem_id;
+    int32_t K;
+    int32_t scheme;
+    double threshold;
+    Motion mv;
+    ObsModel obs;
+    double init_sd[4];
+    GmmPrior prior;
+    double mu_sd;
+    void *state[2];
+    double *lw;
+    int32_t *anc;
+    const double *data;
+    double *hist;
+    int64_t hist_len;
+    double *scalars;
+    TilePartial *partials;
+    double *prefix;
+    double *mon;
+    int32_t *counters;
+    const double *sched;  // batched GMM: [T+1][4] = alpha_t and the three block scales
+};
+
 struct Ctx {
     smc_config cfg;
     smc_buffers buf;
@@ -50,10 +112,6 @@ struct Ctx {
     int32_t mon_pending_step = -1;
     int mon_pending_rows = 0;
     double *mon_pending_out = nullptr;
-    // Student-t / Gaussian observation constants (CV).
-    double obs_const = 0.0;
-    double obs_half_nu1 = 0.0;
-    double obs_inv_scale = 0.0;
     std::string last_error;
 
     void *state_ptr() const { return cur == 0 ? buf.state : buf.state_alt; }
@@ -71,6 +129,10 @@ struct Ctx {
 enum Counter : int { CNT_ERR = 0, CNT_ACC0 = 1, CNT_ACC1 = 2, CNT_ACC2 = 3 };
 
 Workspace plan_workspace(const smc_config &cfg);
+
+// Problem descriptor of a single-problem context (state[0] = the buffer the
+// state currently lives in).
+Prob make_prob(const Ctx &c);
 
 // --- core launchers (smc_core.hip) ---
 hipError_t launch_reset_scalars(Ctx &c);
@@ -95,6 +157,27 @@ hipError_t launch_gmm_move(Ctx &c, int32_t step, const smc_move_args &a, bool ga
 hipError_t launch_gmm_loglik_grad(const double *mu, const double *eta, const double *z,
                                   int64_t n, int32_t K, const double *y, int64_t n_data,
                                   double *loglik, double *grad, hipStream_t stream);
+int gmm_waves(int64_t n, int64_t nd);
+
+// --- batched launchers (a table of Prob and (problem, tile) maps) ---
+hipError_t launch_pf_init_batch(const Prob *probs, const int2 *map, int64_t tiles, hipStream_t s);
+hipError_t launch_pf_move_batch(const Prob *probs, const int2 *map, int64_t tiles,
+                                const int32_t *step, hipStream_t s);
+hipError_t launch_finalize_batch(const Prob *probs, int32_t nprob, const int32_t *step,
+                                 hipStream_t s);
+hipError_t launch_resample_batch(const Prob *probs, const int2 *map, int64_t tiles,
+                                 const int32_t *step, hipStream_t s);
+hipError_t launch_reset_scalars_batch(const Prob *probs, int32_t nprob, hipStream_t s);
+hipError_t launch_set_step(int32_t *step, int32_t value, int32_t add, hipStream_t s);
+hipError_t launch_gmm_init_batch(const Prob *probs, const int2 *map64, int64_t tiles64, int K,
+                                 int W, bool mala, hipStream_t s);
+hipError_t launch_gmm_block_batch(const Prob *probs, const int2 *map64, int64_t tiles64, int K,
+                                  const int32_t *step, int W, int block, int sweep, int first,
+                                  bool mala, hipStream_t s);
+hipError_t launch_gmm_reweight_batch(const Prob *probs, const int2 *map, int64_t tiles,
+                                     const int32_t *step, hipStream_t s);
+hipError_t launch_const_partials_batch(const Prob *probs, const int2 *map, int64_t tiles,
+                                       hipStream_t s);
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

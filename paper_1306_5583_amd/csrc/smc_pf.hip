@@ -6,56 +6,28 @@
 // float.  Per particle-step the fused sweep moves 4 state elements in and
 // out and the log-weight in and out: 80 B (double state) or 48 B (float
 // state), plus 4 B of ancestor index after a resample.
+//
+// Every kernel body is a per-tile device function of a problem descriptor,
+// launched either for one problem (blockIdx = tile) or for a batch of
+// problems (blockIdx -> (problem, tile) through a map).
 #include <math.h>
 
 #include "smc_internal.hpp"
 
 namespace smc {
 
-// Observation log-density of one coordinate: Student-t with nu degrees of
-// freedom and scale s,  c - (nu+1)/2 log1p(((y-pos)/s)^2 / nu), or Gaussian
-// c - ((y-pos)/s)^2 / 2 when gaussian != 0.
-// The two coordinates are independent, so their Student-t terms combine
-// into one logarithm: log1p(a) + log1p(b) = log((1 + a)(1 + b)).
-struct ObsModel {
-    double c, half_nu1, inv_nu, inv_s;
-    int gaussian;
-    __device__ __forceinline__ double operator()(double px, double yx, double py, double yy) const
-    {
-        const double rx = (yx - px) * inv_s;
-        const double ry = (yy - py) * inv_s;
-        if (gaussian)
-            return (c + c) - 0.5 * (rx * rx + ry * ry);
-        const double q = fma(rx * rx, inv_nu, 1.0) * fma(ry * ry, inv_nu, 1.0);
-        return (c + c) - half_nu1 * log_d(q);
-    }
-};
-
-struct Motion {
-    double dt, sd_pos, sd_vel;
-};
-
-static ObsModel make_obs(const Ctx &c)
-{
-    ObsModel o;
-    o.c = c.obs_const;
-    o.half_nu1 = c.obs_half_nu1;
-    o.inv_nu = isinf(c.cfg.obs_nu) ? 0.0 : 1.0 / c.cfg.obs_nu;
-    o.inv_s = c.obs_inv_scale;
-    o.gaussian = isinf(c.cfg.obs_nu) ? 1 : 0;
-    return o;
-}
-
+// Prior draws of one tile: x_0 ~ N(0, diag(init_sd^2)) and the weight of the
+// first observation; tile partial of the log-weights.
 template <typename T>
-__global__ __launch_bounds__(TPB) void pf_init_kernel(T *__restrict__ x, double *__restrict__ lw,
-                                                      int64_t n, Key key, uint32_t p,
-                                                      double4 init_sd,
-                                                      const double *__restrict__ y0, ObsModel obs,
-                                                      TilePartial *__restrict__ part)
+__device__ __forceinline__ void pf_init_tile(const Prob &P, T *__restrict__ x, int64_t tile)
 {
     __shared__ double red[NWAVES];
-    const int64_t base = (int64_t)blockIdx.x * TILE;
-    const double yx = y0[0], yy = y0[1];
+    const int64_t n = P.n;
+    double *__restrict__ lw = P.lw;
+    const int64_t base = tile * TILE;
+    const double yx = P.data[0], yy = P.data[1];
+    const Key key = P.key;
+    const uint32_t p = P.problem_id;
     double lwv[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
@@ -67,42 +39,42 @@ __global__ __launch_bounds__(TPB) void pf_init_kernel(T *__restrict__ x, double 
         if constexpr (sizeof(T) == 8) {
             const double2 a = normal2(draw(key, (uint32_t)i, 0, TAG_INIT, 0, p));
             const double2 b = normal2(draw(key, (uint32_t)i, 0, TAG_INIT, 1, p));
-            s0 = init_sd.x * a.x;
-            s1 = init_sd.y * a.y;
-            s2 = init_sd.z * b.x;
-            s3 = init_sd.w * b.y;
+            s0 = P.init_sd[0] * a.x;
+            s1 = P.init_sd[1] * a.y;
+            s2 = P.init_sd[2] * b.x;
+            s3 = P.init_sd[3] * b.y;
         } else {
             const float4 z = normal4f(draw(key, (uint32_t)i, 0, TAG_INIT, 0, p));
-            s0 = (float)init_sd.x * z.x;
-            s1 = (float)init_sd.y * z.y;
-            s2 = (float)init_sd.z * z.z;
-            s3 = (float)init_sd.w * z.w;
+            s0 = (float)P.init_sd[0] * z.x;
+            s1 = (float)P.init_sd[1] * z.y;
+            s2 = (float)P.init_sd[2] * z.z;
+            s3 = (float)P.init_sd[3] * z.w;
         }
         x[i] = s0;
         x[n + i] = s1;
         x[2 * n + i] = s2;
         x[3 * n + i] = s3;
-        const double l = obs((double)s0, yx, (double)s1, yy);
+        const double l = P.obs((double)s0, yx, (double)s1, yy);
         lw[i] = l;
         lwv[k] = l;
     }
-    tile_partial(lwv, part + blockIdx.x, red);
+    tile_partial(lwv, P.partials + tile, red);
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void pf_init_kernel(Prob P)
+{
+    pf_init_tile<T>(P, (T *)P.state[0], blockIdx.x);
 }
 
 hipError_t launch_pf_init(Ctx &c)
 {
-    const Key key = make_key(c.cfg.seed);
-    const double4 sd = make_double4(c.cfg.init_sd[0], c.cfg.init_sd[1], c.cfg.init_sd[2],
-                                    c.cfg.init_sd[3]);
+    const Prob P = make_prob(c);
     const dim3 grid((unsigned)c.ntiles);
     if (c.elem_bytes == 4)
-        hipLaunchKernelGGL(pf_init_kernel<float>, grid, dim3(TPB), 0, c.stream,
-                           (float *)c.state_ptr(), c.buf.log_weight, c.n, key, c.cfg.problem_id,
-                           sd, c.buf.data, make_obs(c), c.partials());
+        hipLaunchKernelGGL(pf_init_kernel<float>, grid, dim3(TPB), 0, c.stream, P);
     else
-        hipLaunchKernelGGL(pf_init_kernel<double>, grid, dim3(TPB), 0, c.stream,
-                           (double *)c.state_ptr(), c.buf.log_weight, c.n, key, c.cfg.problem_id,
-                           sd, c.buf.data, make_obs(c), c.partials());
+        hipLaunchKernelGGL(pf_init_kernel<double>, grid, dim3(TPB), 0, c.stream, P);
     return hipGetLastError();
 }
 
@@ -114,24 +86,30 @@ hipError_t launch_pf_init(Ctx &c)
 // monitor of the previous step: w_i = 1 after a resample, else
 // exp(lw_i - M)), column-major into mon[5][ntiles].
 template <typename T, bool FUSE, bool MON>
-__global__ __launch_bounds__(TPB) void pf_move_kernel(
-    const T *__restrict__ xin, T *__restrict__ xout, double *__restrict__ lw,
-    const int32_t *__restrict__ anc, const double *__restrict__ scalars, int gather_check,
-    int reset_check, int64_t n, Key key, uint32_t t, uint32_t p, Motion mv,
-    const double *__restrict__ y, ObsModel obs, TilePartial *__restrict__ part,
-    double *__restrict__ mon, int64_t ntiles)
+__device__ __forceinline__ void pf_move_tile(const Prob &P, const T *__restrict__ xin,
+                                             T *__restrict__ xout, int64_t tile, uint32_t t,
+                                             const double *__restrict__ y, bool gather_check,
+                                             bool reset_check)
 {
     __shared__ double red[NWAVES];
-    const bool resampled = (gather_check | reset_check) ? scalars[SMC_S_RESAMPLED] != 0.0 : false;
+    const int64_t n = P.n;
+    double *__restrict__ lw = P.lw;
+    const int32_t *__restrict__ anc = P.anc;
+    const bool resampled =
+        (gather_check || reset_check) ? P.scalars[SMC_S_RESAMPLED] != 0.0 : false;
     const bool gather = gather_check && resampled;
     const bool reset = reset_check && resampled;
-    const int64_t base = (int64_t)blockIdx.x * TILE;
+    const int64_t base = tile * TILE;
+    const Key key = P.key;
+    const uint32_t p = P.problem_id;
+    const Motion mv = P.mv;
+    const ObsModel obs = P.obs;
     double yx = 0.0, yy = 0.0;
     if (FUSE) {
         yx = y[0];
         yy = y[1];
     }
-    const double M = MON ? scalars[SMC_S_M] : 0.0;
+    const double M = MON ? P.scalars[SMC_S_M] : 0.0;
     double ms[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double lwv[ITEMS];
 #pragma unroll
@@ -181,29 +159,34 @@ __global__ __launch_bounds__(TPB) void pf_move_kernel(
         }
     }
     if (FUSE)
-        tile_partial(lwv, part + blockIdx.x, red);
+        tile_partial(lwv, P.partials + tile, red);
     if (MON) {
 #pragma unroll
         for (int r = 0; r < 5; ++r) {
             const double v = block_sum<NWAVES>(ms[r], red);
             if (threadIdx.x == 0)
-                mon[(int64_t)r * ntiles + blockIdx.x] = v;
+                P.mon[(int64_t)r * P.ntiles + tile] = v;
         }
     }
+}
+
+template <typename T, bool FUSE, bool MON>
+__global__ __launch_bounds__(TPB) void pf_move_kernel(Prob P, uint32_t t, int32_t obs_index,
+                                                      int gather_check, int reset_check)
+{
+    pf_move_tile<T, FUSE, MON>(P, (const T *)P.state[0], (T *)P.state[1], blockIdx.x, t,
+                               P.data + 2 * (int64_t)obs_index, gather_check != 0,
+                               reset_check != 0);
 }
 
 template <typename T, bool FUSE, bool MON>
 static void launch_move_t(Ctx &c, int32_t step, int32_t obs_index, bool gather_check,
                           bool reset_check)
 {
-    const Key key = make_key(c.cfg.seed);
-    const Motion mv{c.cfg.dt, c.cfg.sd_pos, c.cfg.sd_vel};
+    const Prob P = make_prob(c);
     hipLaunchKernelGGL((pf_move_kernel<T, FUSE, MON>), dim3((unsigned)c.ntiles), dim3(TPB), 0,
-                       c.stream, (const T *)c.state_ptr(), (T *)c.other_ptr(), c.buf.log_weight,
-                       c.buf.ancestors, c.buf.scalars, (int)gather_check, (int)reset_check, c.n,
-                       key, (uint32_t)step, c.cfg.problem_id, mv,
-                       c.buf.data + 2 * (int64_t)obs_index, make_obs(c), c.partials(), c.mon(),
-                       c.ntiles);
+                       c.stream, P, (uint32_t)step, obs_index, (int)gather_check,
+                       (int)reset_check);
 }
 
 hipError_t launch_pf_move(Ctx &c, int32_t step, int32_t obs_index, bool fuse, bool gather_check,
@@ -232,17 +215,16 @@ hipError_t launch_pf_move(Ctx &c, int32_t step, int32_t obs_index, bool fuse, bo
 // Unfused weighting at the current state (Eq. si with the observation
 // density as the incremental weight).
 template <typename T>
-__global__ __launch_bounds__(TPB) void pf_reweight_kernel(const T *__restrict__ x,
-                                                          double *__restrict__ lw,
-                                                          const double *__restrict__ scalars,
-                                                          int reset_check, int64_t n,
-                                                          const double *__restrict__ y,
-                                                          ObsModel obs,
-                                                          TilePartial *__restrict__ part)
+__global__ __launch_bounds__(TPB) void pf_reweight_kernel(Prob P, int reset_check,
+                                                          int32_t obs_index)
 {
     __shared__ double red[NWAVES];
-    const bool reset = reset_check && scalars[SMC_S_RESAMPLED] != 0.0;
+    const T *__restrict__ x = (const T *)P.state[0];
+    const int64_t n = P.n;
+    double *__restrict__ lw = P.lw;
+    const bool reset = reset_check && P.scalars[SMC_S_RESAMPLED] != 0.0;
     const int64_t base = (int64_t)blockIdx.x * TILE;
+    const double *y = P.data + 2 * (int64_t)obs_index;
     const double yx = y[0], yy = y[1];
     double lwv[ITEMS];
 #pragma unroll
@@ -251,26 +233,69 @@ __global__ __launch_bounds__(TPB) void pf_reweight_kernel(const T *__restrict__ 
         lwv[k] = -INFINITY;
         if (i >= n)
             continue;
-        const double inc = obs((double)x[i], yx, (double)x[n + i], yy);
+        const double inc = P.obs((double)x[i], yx, (double)x[n + i], yy);
         const double l = (reset ? 0.0 : lw[i]) + inc;
         lw[i] = l;
         lwv[k] = l;
     }
-    tile_partial(lwv, part + blockIdx.x, red);
+    tile_partial(lwv, P.partials + blockIdx.x, red);
 }
 
 hipError_t launch_pf_reweight(Ctx &c, int32_t obs_index, bool reset_check)
 {
+    const Prob P = make_prob(c);
     const dim3 grid((unsigned)c.ntiles);
-    const double *y = c.buf.data + 2 * (int64_t)obs_index;
     if (c.elem_bytes == 4)
-        hipLaunchKernelGGL(pf_reweight_kernel<float>, grid, dim3(TPB), 0, c.stream,
-                           (const float *)c.state_ptr(), c.buf.log_weight, c.buf.scalars,
-                           (int)reset_check, c.n, y, make_obs(c), c.partials());
+        hipLaunchKernelGGL(pf_reweight_kernel<float>, grid, dim3(TPB), 0, c.stream, P,
+                           (int)reset_check, obs_index);
     else
-        hipLaunchKernelGGL(pf_reweight_kernel<double>, grid, dim3(TPB), 0, c.stream,
-                           (const double *)c.state_ptr(), c.buf.log_weight, c.buf.scalars,
-                           (int)reset_check, c.n, y, make_obs(c), c.partials());
+        hipLaunchKernelGGL(pf_reweight_kernel<double>, grid, dim3(TPB), 0, c.stream, P,
+                           (int)reset_check, obs_index);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: blockIdx -> (problem, tile) through `map`; the step t is
+// read from the device (so one captured graph serves every step); the state
+// of step t lives in state[t & 1].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void pf_init_batch_kernel(const Prob *__restrict__ probs,
+                                                            const int2 *__restrict__ map)
+{
+    const int2 pm = map[blockIdx.x];
+    const Prob &P = probs[pm.x];
+    pf_init_tile<double>(P, (double *)P.state[0], pm.y);
+}
+
+__global__ __launch_bounds__(TPB) void pf_move_batch_kernel(const Prob *__restrict__ probs,
+                                                            const int2 *__restrict__ map,
+                                                            const int32_t *__restrict__ step)
+{
+    const int2 pm = map[blockIdx.x];
+    const Prob &P = probs[pm.x];
+    const int32_t t = *step;
+    const double *xin = (const double *)P.state[(t - 1) & 1];
+    double *xout = (double *)P.state[t & 1];
+    const int32_t obs = t < P.n_data ? t : (int32_t)P.n_data - 1;
+    pf_move_tile<double, true, true>(P, xin, xout, pm.y, (uint32_t)t, P.data + 2 * (int64_t)obs,
+                                     true, true);
+}
+
+hipError_t launch_pf_init_batch(const Prob *probs, const int2 *map, int64_t tiles, hipStream_t s)
+{
+    if (tiles == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(pf_init_batch_kernel, dim3((unsigned)tiles), dim3(TPB), 0, s, probs, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_pf_move_batch(const Prob *probs, const int2 *map, int64_t tiles,
+                                const int32_t *step, hipStream_t s)
+{
+    if (tiles == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(pf_move_batch_kernel, dim3((unsigned)tiles), dim3(TPB), 0, s, probs, map,
+                       step);
     return hipGetLastError();
 }
 
