@@ -275,6 +275,54 @@ smc_status smc_gmm_loglik_grad(const double *mu, const double *eta, const double
 smc_status smc_draw_words(uint64_t seed, uint32_t step, uint32_t tag, uint32_t call,
                           uint32_t problem, int64_t n, uint32_t *out, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent filters and samplers of different sizes
+ * advanced together.  Each phase of a step (move / reweight, normalisation,
+ * resampling, each Metropolis block) is ONE launch covering every problem's
+ * tiles, the step index lives on the device, and a step can be captured
+ * once into a HIP graph and replayed.  Every problem computes exactly what
+ * its own single-problem context would (same kernels, same Philox counters
+ * with its problem_id); the batch only changes how the work is launched.
+ * Restrictions: systematic resampling, double-precision tracking state,
+ * the same move kind and sweep count for all mixture samplers.
+ * ------------------------------------------------------------------------ */
+typedef struct smc_batch smc_batch;
+
+typedef struct smc_batch_problem {
+    smc_config cfg;          /* as for smc_create */
+    smc_buffers buf;         /* the problem's own device buffers (as for smc_create) */
+    const double *schedule;  /* GMM: device [schedule_len][4] = alpha_t and the mean,
+                                log-precision and logit block scales of step t; NULL for CV */
+    int32_t schedule_len;    /* GMM: rows of schedule (steps + 1) */
+} smc_batch_problem;
+
+/* Device bytes of the batch table (problem descriptors, tile maps, step
+ * counter) the caller must provide to smc_batch_create. */
+smc_status smc_batch_table_size(const smc_batch_problem *probs, int32_t nprob, size_t *bytes);
+smc_status smc_batch_create(const smc_batch_problem *probs, int32_t nprob, void *table,
+                            size_t table_bytes, void *hip_stream, smc_batch **out);
+smc_status smc_batch_destroy(smc_batch *b);
+/* Picks the waves per 64-particle tile of every mixture-size group by timing
+ * the likelihood kernel on the batch's own shapes (repeats launches per
+ * candidate); reads / extends a text cache keyed by device, K and size
+ * bucket when cache_path is non-NULL.  Leaves the state undefined: call
+ * smc_batch_init afterwards. */
+smc_status smc_batch_autotune(smc_batch *b, int32_t repeats, const char *cache_path);
+smc_status smc_batch_waves(const smc_batch *b, int32_t K, int32_t *waves);
+/* Initialisation of every problem (as smc_init, then the t = 0
+ * normalisation and resampling decision); device step counter = 0. */
+smc_status smc_batch_init(smc_batch *b);
+/* Enqueues one step of every problem (step index = device counter + 1). */
+smc_status smc_batch_step(smc_batch *b);
+/* Captures one step into a HIP graph (replaces a previous capture). */
+smc_status smc_batch_capture(smc_batch *b);
+/* Launches the captured step. */
+smc_status smc_batch_replay(smc_batch *b);
+/* Synchronises and checks every problem's device error word; *first_bad
+ * receives the first failing problem or -1. */
+smc_status smc_batch_check(smc_batch *b, int32_t *first_bad);
+const char *smc_batch_last_error(const smc_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,5 +12,7 @@ from .sampler import GmmSampler, ParticleFilter, mala_scales, rw_scales  # noqa:
 
 from .autograd import GmmLogLik, gmm_loglik  # noqa: E402
 
+from .batch import BatchRunner, GmmSpec, PfSpec  # noqa: E402
+
 __all__ = ["ParticleFilter", "GmmSampler", "GmmLogLik", "gmm_loglik", "rw_scales",
-           "mala_scales", "SmcError"]
+           "mala_scales", "SmcError", "BatchRunner", "PfSpec", "GmmSpec"]

@@ -70,6 +70,11 @@ class smc_reweight_args(ctypes.Structure):
     _fields_ = [("obs_index", _i32), ("dalpha", _d)]
 
 
+class smc_batch_problem(ctypes.Structure):
+    _fields_ = [("cfg", smc_config), ("buf", smc_buffers), ("schedule", _vp),
+                ("schedule_len", _i32)]
+
+
 class SmcError(RuntimeError):
     def __init__(self, status, where, detail=""):
         self.status = status
@@ -114,6 +119,18 @@ def load() -> ctypes.CDLL:
         "smc_last_error": (ctypes.c_char_p, [_vp]),
         "smc_gmm_loglik_grad": (st, [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp, _vp, _vp]),
         "smc_draw_words": (st, [_u64, _u32, _u32, _u32, _u32, _i64, _vp, _vp]),
+        "smc_batch_table_size": (st, [P(smc_batch_problem), _i32, P(ctypes.c_size_t)]),
+        "smc_batch_create": (st, [P(smc_batch_problem), _i32, _vp, ctypes.c_size_t, _vp,
+                                  P(_vp)]),
+        "smc_batch_destroy": (st, [_vp]),
+        "smc_batch_autotune": (st, [_vp, _i32, ctypes.c_char_p]),
+        "smc_batch_waves": (st, [_vp, _i32, P(_i32)]),
+        "smc_batch_init": (st, [_vp]),
+        "smc_batch_step": (st, [_vp]),
+        "smc_batch_capture": (st, [_vp]),
+        "smc_batch_replay": (st, [_vp]),
+        "smc_batch_check": (st, [_vp, P(_i32)]),
+        "smc_batch_last_error": (ctypes.c_char_p, [_vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -128,14 +145,19 @@ def exported_symbols():
             "smc_destroy", "smc_set_stream", "smc_init", "smc_move", "smc_reweight", "smc_ess",
             "smc_resample", "smc_monitor", "smc_gather", "smc_current_state",
             "smc_read_scalars", "smc_check", "smc_last_error", "smc_gmm_loglik_grad",
-            "smc_draw_words"]
+            "smc_draw_words", "smc_batch_table_size", "smc_batch_create", "smc_batch_destroy",
+            "smc_batch_autotune", "smc_batch_waves", "smc_batch_init", "smc_batch_step",
+            "smc_batch_capture", "smc_batch_replay", "smc_batch_check", "smc_batch_last_error"]
 
 
-def _check(status, where, ctx=None):
+def _check(status, where, ctx=None, batch=None):
     if status != SMC_OK:
         detail = ""
         if ctx is not None:
             msg = load().smc_last_error(ctx)
+            detail = msg.decode() if msg else ""
+        elif batch is not None:
+            msg = load().smc_batch_last_error(batch)
             detail = msg.decode() if msg else ""
         raise SmcError(status, where, detail)
 
@@ -256,6 +278,68 @@ def smc_gmm_loglik_grad(mu_ptr, eta_ptr, z_ptr, n, K, y_ptr, n_data, ll_ptr, gra
 def smc_draw_words(seed, step, tag, call, problem, n, out_ptr, stream_handle):
     _check(load().smc_draw_words(seed, step, tag, call, problem, n, _vp(out_ptr),
                                  _vp(stream_handle)), "smc_draw_words")
+
+
+# ------------------------------------------------------------------ batch ---
+
+def _problem_array(probs):
+    arr = (smc_batch_problem * len(probs))()
+    for i, p in enumerate(probs):
+        arr[i] = p
+    return arr
+
+
+def smc_batch_table_size(probs):
+    arr = _problem_array(probs)
+    b = ctypes.c_size_t()
+    _check(load().smc_batch_table_size(arr, len(probs), ctypes.byref(b)), "smc_batch_table_size")
+    return b.value
+
+
+def smc_batch_create(probs, table_ptr, table_bytes, stream_handle):
+    arr = _problem_array(probs)
+    h = _vp()
+    _check(load().smc_batch_create(arr, len(probs), _vp(table_ptr), table_bytes,
+                                   _vp(stream_handle), ctypes.byref(h)), "smc_batch_create")
+    return h
+
+
+def smc_batch_destroy(b):
+    _check(load().smc_batch_destroy(b), "smc_batch_destroy")
+
+
+def smc_batch_autotune(b, repeats, cache_path=None):
+    _check(load().smc_batch_autotune(b, repeats, cache_path.encode() if cache_path else None),
+           "smc_batch_autotune", batch=b)
+
+
+def smc_batch_waves(b, K):
+    w = _i32()
+    _check(load().smc_batch_waves(b, K, ctypes.byref(w)), "smc_batch_waves", batch=b)
+    return w.value
+
+
+def smc_batch_init(b):
+    _check(load().smc_batch_init(b), "smc_batch_init", batch=b)
+
+
+def smc_batch_step(b):
+    _check(load().smc_batch_step(b), "smc_batch_step", batch=b)
+
+
+def smc_batch_capture(b):
+    _check(load().smc_batch_capture(b), "smc_batch_capture", batch=b)
+
+
+def smc_batch_replay(b):
+    _check(load().smc_batch_replay(b), "smc_batch_replay", batch=b)
+
+
+def smc_batch_check(b):
+    """Returns (status, first_bad_problem) without raising."""
+    bad = _i32()
+    st = load().smc_batch_check(b, ctypes.byref(bad))
+    return st, bad.value
 
 
 INF = math.inf

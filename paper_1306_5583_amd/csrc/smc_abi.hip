@@ -51,7 +51,7 @@ Workspace plan_workspace(const smc_config &cfg)
     return w;
 }
 
-static Prob prob_from(const smc_config &cfg, const smc_buffers &buf, const Workspace &ws,
+Prob prob_from(const smc_config &cfg, const smc_buffers &buf, const Workspace &ws,
                       void *s0, void *s1)
 {
     Prob P{};
@@ -110,7 +110,7 @@ static Prob prob_from(const smc_config &cfg, const smc_buffers &buf, const Works
 
 Prob make_prob(const Ctx &c) { return prob_from(c.cfg, c.buf, c.ws, c.state_ptr(), c.other_ptr()); }
 
-static smc_status validate_config(const smc_config *cfg, std::string &err)
+smc_status validate_config(const smc_config *cfg, std::string &err)
 {
     if (!cfg) {
         err = "config is NULL";
@@ -187,7 +187,7 @@ static smc_status validate_config(const smc_config *cfg, std::string &err)
 
 static bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
-static smc_status validate_buffers(const smc_config &cfg, const smc_buffers *b, std::string &err)
+smc_status validate_buffers(const smc_config &cfg, const smc_buffers *b, std::string &err)
 {
     if (!b) {
         err = "buffers is NULL";
@@ -222,7 +222,7 @@ static smc_status validate_buffers(const smc_config &cfg, const smc_buffers *b, 
     return SMC_OK;
 }
 
-static smc_status device_ok(std::string &err)
+smc_status device_ok(std::string &err)
 {
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {

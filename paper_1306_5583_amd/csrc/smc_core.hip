@@ -12,13 +12,19 @@ namespace smc {
 // ---------------------------------------------------------------------------
 // Scalar block reset (initialisation): L = log N, log Z = 0.
 // ---------------------------------------------------------------------------
-__global__ void reset_scalars_kernel(double *scalars, int32_t *counters, int64_t n)
+// Scalars and counters to their t = 0 values; the history rows (whose
+// acceptance columns are accumulated) to zero.
+__global__ void reset_scalars_kernel(double *scalars, int32_t *counters, int64_t n, double *hist,
+                                     int64_t hist_len)
 {
     const int t = threadIdx.x;
     if (t < SMC_SCALARS_LEN)
         scalars[t] = 0.0;
     if (t < 16)
         counters[t] = 0;
+    if (hist)
+        for (int64_t k = t; k < hist_len * SMC_HIST_COLS; k += blockDim.x)
+            hist[k] = 0.0;
     __syncthreads();
     if (t == 0) {
         scalars[SMC_S_L] = log((double)n);
@@ -29,8 +35,8 @@ __global__ void reset_scalars_kernel(double *scalars, int32_t *counters, int64_t
 
 hipError_t launch_reset_scalars(Ctx &c)
 {
-    hipLaunchKernelGGL(reset_scalars_kernel, dim3(1), dim3(64), 0, c.stream, c.buf.scalars,
-                       c.counters(), c.n);
+    hipLaunchKernelGGL(reset_scalars_kernel, dim3(1), dim3(256), 0, c.stream, c.buf.scalars,
+                       c.counters(), c.n, c.buf.history, c.buf.history ? c.buf.history_len : 0);
     return hipGetLastError();
 }
 
@@ -340,6 +346,9 @@ __global__ void reset_scalars_batch_kernel(const Prob *__restrict__ probs)
         P.scalars[t] = 0.0;
     if (t < 16)
         P.counters[t] = 0;
+    if (P.hist)
+        for (int64_t k = t; k < P.hist_len * SMC_HIST_COLS; k += blockDim.x)
+            P.hist[k] = 0.0;
     __syncthreads();
     if (t == 0) {
         P.scalars[SMC_S_L] = log((double)P.n);

@@ -133,6 +133,11 @@ Workspace plan_workspace(const smc_config &cfg);
 // Problem descriptor of a single-problem context (state[0] = the buffer the
 // state currently lives in).
 Prob make_prob(const Ctx &c);
+Prob prob_from(const smc_config &cfg, const smc_buffers &buf, const Workspace &ws, void *s0,
+               void *s1);
+smc_status validate_config(const smc_config *cfg, std::string &err);
+smc_status validate_buffers(const smc_config &cfg, const smc_buffers *b, std::string &err);
+smc_status device_ok(std::string &err);
 
 // --- core launchers (smc_core.hip) ---
 hipError_t launch_reset_scalars(Ctx &c);

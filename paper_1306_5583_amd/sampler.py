@@ -17,11 +17,12 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else t.data_ptr()
 
 
-class _Base:
-    """Common buffer set: state ping-pong pair, log-weights, ancestors,
-    data, history, workspace and the scalar block."""
+class ProblemBuffers:
+    """Device buffers of one problem: state ping-pong pair, log-weights,
+    ancestors, data, history, workspace and the scalar block, with the
+    smc_buffers view the C ABI takes."""
 
-    def __init__(self, cfg, data: torch.Tensor, history_len: int, device, stream):
+    def __init__(self, cfg, data: torch.Tensor, history_len: int, device):
         self.cfg = cfg
         self.device = torch.device(device)
         rows, eb = L.smc_state_rows(cfg)
@@ -53,9 +54,17 @@ class _Base:
         b.workspace = self.ws_ptr
         b.workspace_bytes = ws
         b.scalars = self.scalars.data_ptr()
-        self._bufs = b
+        self.view = b
+
+
+class _Base(ProblemBuffers):
+    """A problem's buffers plus its single-problem context."""
+
+    def __init__(self, cfg, data: torch.Tensor, history_len: int, device, stream):
+        super().__init__(cfg, data, history_len, device)
+        self._bufs = self.view
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.ctx = L.smc_create(cfg, b, self.stream.cuda_stream)
+        self.ctx = L.smc_create(cfg, self.view, self.stream.cuda_stream)
 
     def close(self):
         if getattr(self, "ctx", None):

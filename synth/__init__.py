@@ -152,3 +152,23 @@ def batched_problems(n_pf: int = 128, n_gmm: int = 32, seed: int = 5583,
 
 # Data seeds of the five workloads (1306 + index).
 DATA_SEED = {k: 1306 + k for k in range(5)}
+
+
+def batched_workload(steps: int = 200, probs: List[BatchProblem] | None = None,
+                     tempering_power: float = 4.0):
+    """Inputs of every problem of a batched run: ``[(kind, kwargs), ...]``
+    with kwargs n, seed, problem_id (the problem's index) and, for "pf",
+    observations y[steps + 1][2] of the problem's own trajectory; for "gmm",
+    K, data y (means spaced in [-5, 5]) and the exponents
+    alphas[steps + 1] = (t / steps)^power."""
+    probs = batched_problems() if probs is None else probs
+    out = []
+    for p, q in enumerate(probs):
+        if q.kind == "pf":
+            _, y = pf_trajectory(steps + 1, q.data_seed)
+            out.append(("pf", dict(n=q.n_particles, y=y, seed=q.seed, problem_id=p)))
+        else:
+            y, _ = gmm_data_spaced(q.n_data, q.K, q.data_seed)
+            out.append(("gmm", dict(n=q.n_particles, y=y, K=q.K, seed=q.seed, problem_id=p,
+                                    alphas=prior_tempering(steps, tempering_power))))
+    return out

@@ -121,3 +121,57 @@ def test_null_context_rejected(L):
     assert lib.smc_init(None) == L.SMC_ERR_INVALID_ARG
     assert lib.smc_resample(None, 0, 0) == L.SMC_ERR_INVALID_ARG
     assert lib.smc_check(None) == L.SMC_ERR_INVALID_ARG
+
+
+def _fake_problem(L, cfg, schedule=None):
+    """A batch entry whose buffer addresses are aligned but never touched:
+    every case below is rejected before any device work."""
+    p = L.smc_batch_problem()
+    p.cfg = cfg
+    b = L.smc_buffers()
+    base = 1 << 32
+    for k, name in enumerate(("state", "state_alt", "log_weight", "ancestors", "data",
+                              "workspace", "scalars")):
+        setattr(b, name, base + (k << 28))
+    b.workspace_bytes = L.smc_workspace_size(cfg)
+    b.history = None
+    b.history_len = 0
+    p.buf = b
+    p.schedule = schedule
+    p.schedule_len = 0 if schedule is None else 11
+    return p
+
+
+def test_batch_host_validation(L):
+    pf = L.make_config(L.SMC_MODEL_CV_TRACK, 5000, n_obs=11)
+    rw = L.make_config(L.SMC_MODEL_GMM_TEMPERED, 3000, K=3, n_data=50)
+    mala = L.make_config(L.SMC_MODEL_GMM_TEMPERED, 3000, K=4, n_data=50,
+                         move_kind=L.SMC_MOVE_MALA)
+    sched = 1 << 40
+    one = L.smc_batch_table_size([_fake_problem(L, pf)])
+    two = L.smc_batch_table_size([_fake_problem(L, pf), _fake_problem(L, rw, sched)])
+    assert 0 < one < two and one % 256 == 0 and two % 256 == 0
+    table = 1 << 44
+
+    def create(probs, nbytes=None):
+        nb = L.smc_batch_table_size(probs) if nbytes is None else nbytes
+        with pytest.raises(L.SmcError) as e:
+            L.smc_batch_create(probs, table, nb, None)
+        return e.value.status
+
+    # resampling other than systematic, FP32 filter state: not batched
+    assert create([_fake_problem(L, L.make_config(L.SMC_MODEL_CV_TRACK, 10, n_obs=3,
+                                                  scheme="multinomial"))]) == \
+        L.SMC_ERR_UNSUPPORTED
+    assert create([_fake_problem(L, L.make_config(L.SMC_MODEL_CV_TRACK, 10, n_obs=3,
+                                                  precision=L.SMC_F32_STATE))]) == \
+        L.SMC_ERR_UNSUPPORTED
+    # samplers of one batch share the move kind
+    assert create([_fake_problem(L, rw, sched), _fake_problem(L, mala, sched)]) == \
+        L.SMC_ERR_UNSUPPORTED
+    # a sampler needs its schedule; the table must be large enough
+    assert create([_fake_problem(L, rw)]) == L.SMC_ERR_INVALID_ARG
+    assert create([_fake_problem(L, pf)], one - 256) == L.SMC_ERR_INVALID_ARG
+    bad = _fake_problem(L, pf)
+    bad.buf.workspace_bytes = 16
+    assert create([bad]) == L.SMC_ERR_INVALID_ARG

@@ -1,0 +1,239 @@
+"""Batched form: many filters and samplers of uneven sizes in one launch per
+phase.  Each problem must be its own single-problem algorithm with its
+problem id in the Philox counter, so the batch is checked (a) against the
+oracle run of each problem, (b) against the single-problem GPU path and
+(c) between eager steps and graph replays."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import assert_close_l1
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_5583_amd as pkg
+    from paper_1306_5583_amd import _lib as L
+    return pkg, L
+
+
+def _say(*a):
+    print("[batch]", *a, flush=True)
+
+
+def _small_workload(steps):
+    """Ragged sizes spanning several tiles; K = 1 included."""
+    rng = np.random.default_rng(41)
+    probs = []
+    for n in (1000, 3001, 5120):
+        probs.append(synth.BatchProblem("pf", n, int(rng.integers(1, 1 << 40)),
+                                        int(rng.integers(1, 1000))))
+    for n, K, nd in ((2048, 3, 90), (1500, 1, 60), (3333, 5, 130), (700, 2, 45)):
+        probs.append(synth.BatchProblem("gmm", n, int(rng.integers(1, 1 << 40)),
+                                        int(rng.integers(1, 1000)), K, nd))
+    return synth.batched_workload(steps, probs)
+
+
+def _specs(pkg, work, move="mala"):
+    out = []
+    for kind, kw in work:
+        if kind == "pf":
+            out.append(pkg.PfSpec(**kw))
+        else:
+            out.append(pkg.GmmSpec(move=move, **kw))
+    return out
+
+
+def _orc_cfg(orc, kind, kw, move):
+    if kind == "pf":
+        return orc.pf_cfg(kw["n"], kw["seed"], problem=kw["problem_id"])
+    return orc.gmm_cfg(kw["n"], kw["seed"], kw["K"], problem=kw["problem_id"], move=move)
+
+
+@pytest.mark.parametrize("move", ["mala", "rw"])
+def test_batch_matches_oracle(lib, orc, move):
+    pkg, L = lib
+    steps = 10
+    work = _small_workload(steps)
+    specs = _specs(pkg, work, move)
+    _say("oracle parity", move, [(k, kw["n"]) for k, kw in work])
+    br = pkg.BatchRunner(specs)
+    br.run(steps, graph=True)
+    br.check()
+    for i, (kind, kw) in enumerate(work):
+        h = br.history_host(i)
+        cfg = _orc_cfg(orc, kind, kw, move)
+        if kind == "pf":
+            logz_o, hist_o, xf_o, _ = orc.pf_run(cfg, kw["y"])
+            scale = max(1.0, np.abs(hist_o[:, 2]).sum())
+            assert abs(br.log_z(i) - logz_o) <= 1e-12 * scale, (i, br.log_z(i), logz_o)
+            assert np.array_equal(h[:steps + 1, L.SMC_H_FLAG], hist_o[:, 1])
+            assert_close_l1(h[:steps + 1, L.SMC_H_ESS], hist_o[:, 0], hist_o[:, 0], 1e-11, "ess")
+            # the monitor of step t is completed by step t + 1's pass
+            assert_close_l1(h[:steps, L.SMC_H_MON:L.SMC_H_MON + 4], hist_o[:steps, 5:9], 20.0,
+                            1e-11, "means")
+            x = br.state(i).cpu().numpy()[:4]
+            if h[steps, L.SMC_H_FLAG] == 1:  # ancestors still pending
+                x = x[:, br.bufs[i].ancestors.cpu().numpy()]
+            assert_close_l1(x, xf_o, np.abs(xf_o) + 1.0, 1e-11, "state")
+        else:
+            sched = pkg.batch.gmm_schedule(kw["alphas"], None, move)
+            logz_o, hist_o, pop_o, _ = orc.gmm_run(cfg, kw["y"], sched[:, 0], sched[:, 1:])
+            scale = max(1.0, np.abs(hist_o[:, 2]).sum())
+            assert abs(br.log_z(i) - logz_o) <= 1e-9 * scale, (i, br.log_z(i), logz_o)
+            assert np.array_equal(h[1:, L.SMC_H_FLAG], hist_o[1:, 1])
+            acc = h[1:, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3]
+            assert np.all(np.abs(acc - hist_o[1:, 5:8]) <= 2), (i, acc, hist_o[1:, 5:8])
+
+
+def test_batch_equals_single_problem_runs(lib):
+    pkg, L = lib
+    steps = 8
+    work = _small_workload(steps)
+    br = pkg.BatchRunner(_specs(pkg, work))
+    br.run(steps, graph=False)
+    br.check()
+    for i, (kind, kw) in enumerate(work):
+        h = br.history_host(i)
+        if kind == "pf":
+            pf = pkg.ParticleFilter(kw["n"], kw["y"], seed=kw["seed"], problem_id=kw["problem_id"])
+            pf.run()
+            hs = pf.history_host()
+            # same kernels, same tiles: identical bits
+            cols = [L.SMC_H_ESS, L.SMC_H_FLAG, L.SMC_H_DLOGZ, L.SMC_H_LOGZ, L.SMC_H_L]
+            assert np.array_equal(h[:, cols], hs[:, cols]), i
+            assert np.array_equal(br.state(i).cpu().numpy(), pf.state().cpu().numpy()), i
+        else:
+            s = pkg.GmmSampler(kw["n"], kw["y"], kw["K"], steps, seed=kw["seed"],
+                               problem_id=kw["problem_id"], move="mala")
+            s.run(kw["alphas"])
+            hs = s.history_host()
+            # the waves per tile may differ: the likelihood sums in another order
+            scale = max(1.0, np.abs(hs[:, L.SMC_H_DLOGZ]).sum())
+            assert abs(br.log_z(i) - s.log_z()) <= 1e-10 * scale, i
+            assert np.array_equal(h[:, L.SMC_H_FLAG], hs[:, L.SMC_H_FLAG]), i
+            assert np.all(np.abs(h[:, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3] -
+                                 hs[:, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3]) <= 2), i
+
+
+def test_graph_replays_equal_eager_steps(lib):
+    pkg, L = lib
+    steps = 6
+    work = _small_workload(steps)
+    a = pkg.BatchRunner(_specs(pkg, work))
+    a.run(steps, graph=False)
+    b = pkg.BatchRunner(_specs(pkg, work))
+    b.run(steps, graph=True)
+    a.check()
+    b.check()
+    for i in range(len(work)):
+        assert np.array_equal(a.history_host(i), b.history_host(i)), i
+        assert np.array_equal(a.state(i).cpu().numpy(), b.state(i).cpu().numpy()), i
+    # a second run on the same buffers (init again, replay the same graph)
+    b.init()
+    for _ in range(steps):
+        b.replay()
+    b.check()
+    for i in range(len(work)):
+        assert np.array_equal(a.history_host(i), b.history_host(i)), i
+
+
+def test_step_limits_and_order(lib):
+    pkg, L = lib
+    work = _small_workload(3)
+    br = pkg.BatchRunner(_specs(pkg, work))
+    with pytest.raises(pkg.SmcError):
+        br.step()  # before init
+    with pytest.raises(pkg.SmcError):
+        br.replay()  # before capture
+    br.init()
+    for _ in range(3):
+        br.step()
+    with pytest.raises(pkg.SmcError):
+        br.step()  # schedules / observations exhausted
+    br.check()
+
+
+def test_autotune_and_cache(lib, tmp_path):
+    pkg, L = lib
+    steps = 5
+    work = _small_workload(steps)
+    cache = str(tmp_path / "tune.txt")
+    br = pkg.BatchRunner(_specs(pkg, work))
+    ref = pkg.BatchRunner(_specs(pkg, work))
+    ref.run(steps, graph=True)
+    br.autotune(repeats=3, cache_path=cache)
+    Ks = sorted({kw["K"] for k, kw in work if k == "gmm"})
+    chosen = {K: br.waves(K) for K in Ks}
+    assert all(w in (1, 2, 4, 8) for w in chosen.values())
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == len(Ks)
+    br.run(steps, graph=True)
+    br.check()
+    for i, (kind, kw) in enumerate(work):
+        scale = max(1.0, np.abs(ref.history_host(i)[:, L.SMC_H_DLOGZ]).sum())
+        assert abs(br.log_z(i) - ref.log_z(i)) <= 1e-10 * scale, i
+    # a second tuner call reads the cache and does not append
+    br2 = pkg.BatchRunner(_specs(pkg, work))
+    br2.autotune(repeats=3, cache_path=cache)
+    assert {K: br2.waves(K) for K in Ks} == chosen
+    assert open(cache).read().strip().splitlines() == lines
+
+
+def test_full_size_batched_workload_sampled(lib, orc):
+    """The 128-filter / 32-sampler workload at its full sizes, a few steps:
+    sampled problems against their single-problem runs, sampled particles'
+    cached log-likelihoods against the oracle, weights and ESS bounds on
+    every problem."""
+    pkg, L = lib
+    steps = 4
+    work = synth.batched_workload(steps)
+    specs = _specs(pkg, work)
+    _say("full-size batch", len(specs), "problems")
+    br = pkg.BatchRunner(specs)
+    br.run(steps, graph=True)
+    br.check()
+    for i in range(len(work)):
+        h = br.history_host(i)
+        n = work[i][1]["n"]
+        ess = h[:steps + 1, L.SMC_H_ESS]
+        assert np.all(ess >= 1.0 - 1e-9) and np.all(ess <= n * (1 + 1e-12)), i
+        assert np.all(np.isfinite(h[:steps + 1, L.SMC_H_LOGZ])), i
+    pf_idx = [i for i, (k, _) in enumerate(work) if k == "pf"]
+    gm_idx = [i for i, (k, _) in enumerate(work) if k == "gmm"]
+    rng = np.random.default_rng(3)
+    for i in list(rng.choice(pf_idx, 3, replace=False)):
+        kw = work[i][1]
+        pf = pkg.ParticleFilter(kw["n"], kw["y"][:steps + 1], seed=kw["seed"],
+                                problem_id=kw["problem_id"])
+        pf.run()
+        assert pf.log_z() == br.log_z(i), i
+    for i in list(rng.choice(gm_idx, 2, replace=False)):
+        kw = work[i][1]
+        s = pkg.GmmSampler(kw["n"], kw["y"], kw["K"], steps, seed=kw["seed"],
+                           problem_id=kw["problem_id"], move="mala")
+        s.run(kw["alphas"][:steps + 1])
+        hs = s.history_host()
+        scale = max(1.0, np.abs(hs[:, L.SMC_H_DLOGZ]).sum())
+        assert abs(s.log_z() - br.log_z(i)) <= 1e-10 * scale, i
+        # cached log-likelihood row of sampled particles against the oracle
+        K = kw["K"]
+        D = 3 * K - 1
+        st = br.state(i).cpu().numpy()
+        for j in rng.integers(0, kw["n"], 6):
+            v = orc.gmm_loglik(st[:D, j], K, kw["y"])
+            assert abs(st[D, j] - v) <= 1e-12 * (abs(v) + kw["y"].size), (i, j)
+    # the oracle end to end on the smallest filter, all its observations
+    small = min(pf_idx, key=lambda i: work[i][1]["n"])
+    kw = work[small][1]
+    logz_o, hist_o, _, _ = orc.pf_run(orc.pf_cfg(kw["n"], kw["seed"], problem=small),
+                                      kw["y"][:steps + 1])
+    assert abs(br.log_z(small) - logz_o) <= 1e-12 * max(1.0, np.abs(hist_o[:, 2]).sum())
