@@ -86,11 +86,30 @@ __device__ __forceinline__ double log_prior_grad(const double (&phi)[3 * K - 1 >
     return pr.rho * (1.0 - (double)K * exp_d(logw[q - 2 * K]));
 }
 
-// Per-lane mixture likelihood accumulator for one particle.
+// Per-lane mixture likelihood accumulator for one particle (Section 5.2.1):
+// log p(y) = log sum_j exp(c_j - (lambda_j / 2) (y - mu_j)^2) with
+// c_j = log omega_j + eta_j / 2 - log(2 pi) / 2, summed over the data.
+//
+// The log-sum-exp of each point runs in base 2: a_j = c_j log2(e) - u_j^2
+// with u_j = g_j (y - mu_j) = g_j y - g_j mu_j, g_j = sqrt(lambda_j log2(e)
+// / 2), the maximum m of the a_j factored out, s = sum_j 2^(a_j - m) in
+// [1, K].  Instead of a logarithm per point, the sums s are multiplied
+// together and the product's logarithm is taken every FLUSH points (a
+// product of at most 64 factors <= 16 stays below 2^256), so
+// log p = ln 2 * sum m + sum log(prod).
+//
+// Gradient (GRAD): with responsibilities r_j = 2^(a_j - m) / s and
+// lambda_j d_j = 2 ln2 g_j u_j, lambda_j d_j^2 / 2 = ln2 u_j^2:
+//   d/d mu_j  = sum r_j lambda_j (y - mu_j)        = 2 ln2 g_j sum r_j u_j
+//   d/d eta_j = sum r_j (1/2 - lambda_j d_j^2 / 2) = sum r_j / 2 - ln2 sum r_j u_j^2
+// accumulated as sum r u (in gmu), sum r u^2 (in geta) and sum r (in gr)
+// and converted once in finish().
 template <int K, bool GRAD>
 struct MixLik {
-    double mu[K], hl[K], c[K];
-    double ll;
+    static constexpr int FLUSH = 64;
+    double g[K], gm[K], c[K];
+    double ll;  // after chunk(): sum of log p(y_k) over the chunk
+    double m2, lsum, prod;
     double gmu[GRAD ? K : 1], geta[GRAD ? K : 1], gr[GRAD ? K : 1];
 
     __device__ __forceinline__ void setup(const double (&phi)[3 * K - 1 > 0 ? 3 * K - 1 : 1],
@@ -98,11 +117,12 @@ struct MixLik {
     {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            mu[j] = phi[j];
-            hl[j] = 0.5 * exp_d(phi[K + j]);
-            c[j] = logw[j] + 0.5 * phi[K + j] - kHalfLog2Pi;
+            g[j] = sqrt((0.5 * detail::kLog2e) * exp_d(phi[K + j]));
+            gm[j] = g[j] * phi[j];
+            c[j] = detail::kLog2e * (logw[j] + 0.5 * phi[K + j] - kHalfLog2Pi);
         }
-        ll = 0.0;
+        ll = m2 = lsum = 0.0;
+        prod = 1.0;
         if (GRAD) {
 #pragma unroll
             for (int j = 0; j < K; ++j)
@@ -112,30 +132,57 @@ struct MixLik {
 
     __device__ __forceinline__ void point(double y)
     {
-        double e[K], d[K];
-        double m = -INFINITY;
+        double e[K], u[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            d[j] = y - mu[j];
-            e[j] = fma(-hl[j] * d[j], d[j], c[j]);
-            m = fmax(m, e[j]);
+            u[j] = fma(g[j], y, -gm[j]);
+            e[j] = fma(-u[j], u[j], c[j]);
         }
+        if constexpr (K == 1) {
+            m2 += e[0];
+            if (GRAD) {
+                gmu[0] += u[0];
+                geta[0] = fma(u[0], u[0], geta[0]);
+                gr[0] += 1.0;
+            }
+            return;
+        }
+        double m = e[0];
+#pragma unroll
+        for (int j = 1; j < K; ++j)
+            m = fmax(m, e[j]);
         double s = 0.0;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            e[j] = exp_d(e[j] - m);
-            s += e[j];
+            e[j] = exp2_nonpos(e[j] - m);
+            s = j == 0 ? e[0] : s + e[j];
         }
-        ll += m + log_d(s);
+        m2 += m;
+        prod *= s;
         if (GRAD) {
-            const double inv = 1.0 / s;
+            // 1/s for s in [1, K]: hardware estimate and two Newton steps
+            double inv = __builtin_amdgcn_rcp(s);
+            inv = fma(inv, fma(-s, inv, 1.0), inv);
+            inv = fma(inv, fma(-s, inv, 1.0), inv);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const double r = e[j] * inv;
-                const double rh = r * hl[j];
-                gmu[j] = fma(2.0 * rh, d[j], gmu[j]);
-                geta[j] = fma(-rh * d[j], d[j], fma(0.5, r, geta[j]));
+                const double ru = r * u[j];
+                gmu[j] += ru;
+                geta[j] = fma(ru, u[j], geta[j]);
                 gr[j] += r;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void finish()
+    {
+        ll = fma(detail::kLn2, m2, lsum);
+        if (GRAD) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                gmu[j] *= (2.0 * detail::kLn2) * g[j];
+                geta[j] = fma(-detail::kLn2, geta[j], 0.5 * gr[j]);
             }
         }
     }
@@ -144,13 +191,21 @@ struct MixLik {
     __device__ __forceinline__ void chunk(const double *__restrict__ y, int64_t k0, int64_t k1)
     {
         int64_t k = k0;
-        for (; k + 2 <= k1; k += 2) {
-            const double y0 = y[k], y1 = y[k + 1];
-            point(y0);
-            point(y1);
+        while (k < k1) {
+            const int64_t kend = min(k + FLUSH, k1);
+            if (K <= 8) {  // two points per iteration while registers allow
+                for (; k + 2 <= kend; k += 2) {
+                    const double y0 = y[k], y1 = y[k + 1];
+                    point(y0);
+                    point(y1);
+                }
+            }
+            for (; k < kend; ++k)
+                point(y[k]);
+            lsum += log_d(prod);
+            prod = 1.0;
         }
-        if (k < k1)
-            point(y[k]);
+        finish();
     }
 
     static constexpr int NACC = GRAD ? 1 + 3 * K : 1;

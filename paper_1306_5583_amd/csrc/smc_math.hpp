@@ -9,6 +9,11 @@
 //  exp_d(x):   x = k ln2 + r with k = rint(x / ln2) and |r| <= ln2/2 (Cody &
 //              Waite reduction with ln2 in two parts), e^r by its Taylor series
 //              to degree 13 (truncation below 5e-18), then scaled by 2^k.
+//  exp2_nonpos(x): 2^x for x <= 0 (the terms of a log-sum-exp taken in base
+//              2): x = k + r with k = rint(x), |r| <= 1/2 exact, 2^r by the
+//              degree-11 polynomial interpolating it at the 12 Chebyshev
+//              nodes of [-1/2, 1/2] (interpolation error 2e-17 relative;
+//              coefficients from gen_exp2_poly.py), scaled by 2^k.
 //  sincospi_d: sin(pi x), cos(pi x) by exact reduction to r = x - n/2,
 //              |r| <= 1/4, and the Taylor series of sin(pi r), cos(pi r)
 //              (truncation below 2e-22 for |pi r| <= pi/4), then the
@@ -43,6 +48,13 @@ constexpr double kExpC[14] = {exp_c(0), exp_c(1), exp_c(2),  exp_c(3),  exp_c(4)
                               exp_c(5), exp_c(6), exp_c(7),  exp_c(8),  exp_c(9),
                               exp_c(10), exp_c(11), exp_c(12), exp_c(13)};
 constexpr double kLog2e = 1.4426950408889634073599246810019;
+constexpr double kLn2 = 0.69314718055994530941723212145818;
+// 2^r ~ sum_j kExp2C[j] r^j on [-1/2, 1/2] (gen_exp2_poly.py)
+constexpr double kExp2C[12] = {
+    0x1.0000000000000p+0,  0x1.62e42fefa39efp-1,  0x1.ebfbdff82c5aep-3,
+    0x1.c6b08d704a0c6p-5,  0x1.3b2ab6fb9f1a5p-7,  0x1.5d87fe78a3f9cp-10,
+    0x1.430913112c61bp-13, 0x1.ffcbfc6da6ed1p-17, 0x1.62bfc2c86d700p-20,
+    0x1.b524ebd13a55fp-24, 0x1.e6228acd1c6e5p-28, 0x1.e9ec1fcb69a7fp-32};
 constexpr double kSinC[10] = {sin_c(0), sin_c(1), sin_c(2), sin_c(3), sin_c(4),
                               sin_c(5), sin_c(6), sin_c(7), sin_c(8), sin_c(9)};
 constexpr double kCosC[10] = {cos_c(0), cos_c(1), cos_c(2), cos_c(3), cos_c(4),
@@ -91,6 +103,21 @@ __host__ __device__ inline double exp_d(double x)
     double v = ldexp(p, (int)k);
     v = (x != x) ? x : v;
     return v;
+}
+
+// 2^x for x <= 0: x below -1100 (and -inf) gives 0 through gradual
+// underflow; so does NaN (the caller guarantees x is not NaN).  2^0 = 1
+// exactly.
+__host__ __device__ inline double exp2_nonpos(double x)
+{
+    const double xc = fmax(x, -1100.0);
+    const double k = rint(xc);
+    const double r = xc - k;  // exact
+    double p = detail::kExp2C[11];
+#pragma unroll
+    for (int j = 10; j >= 0; --j)
+        p = fma(p, r, detail::kExp2C[j]);
+    return ldexp(p, (int)k);
 }
 
 // sin(pi x) and cos(pi x) for |x| < 2^50.

@@ -65,6 +65,16 @@ int main()
                              std::isnan(smc::exp_d(NAN)) &&
                              std::fabs(smc::exp_d(-740.0) - std::exp(-740.0)) <= 1e-320;
     std::printf("exp_ulp %.3f\nexp_special %d\n", e_exp, (int)exp_special);
+    double e_exp2 = 0;
+    for (int i = 0; i < 2000000; ++i) {
+        const double x = i % 5 == 0 ? -U(g) : -1022.0 * U(g);
+        e_exp2 = std::fmax(e_exp2, ulp_err(smc::exp2_nonpos(x), exp2l((long double)x)));
+    }
+    const bool exp2_special = smc::exp2_nonpos(0.0) == 1.0 && smc::exp2_nonpos(-INFINITY) == 0.0 &&
+                              smc::exp2_nonpos(-1e300) == 0.0 && smc::exp2_nonpos(-1.0) == 0.5 &&
+                              smc::exp2_nonpos(-1074.0) == std::ldexp(1.0, -1074) &&
+                              smc::exp2_nonpos(-1080.0) == 0.0;
+    std::printf("exp2_ulp %.3f\nexp2_special %d\n", e_exp2, (int)exp2_special);
     const bool special = std::isinf(smc::log_d(0.0)) && smc::log_d(0.0) < 0 &&
                          std::isnan(smc::log_d(-1.0)) && std::isinf(smc::log_d(INFINITY)) &&
                          smc::log_d(1.0) == 0.0 && std::isnan(smc::log_d(NAN));

@@ -1,4 +1,4 @@
-"""Accuracy of the sweep's own double-precision log and sin/cos(pi x)
+"""Accuracy of the sweep's own double-precision log, exp, 2^x and sin/cos(pi x)
 (paper_1306_5583_amd/csrc/smc_math.hpp), compiled for the host and checked
 against long-double references over millions of arguments."""
 import os
@@ -27,3 +27,5 @@ def test_math_functions_within_few_ulp(tmp_path):
     assert vals["special"] == "1"
     assert float(vals["exp_ulp"]) < 4.0
     assert vals["exp_special"] == "1"
+    assert float(vals["exp2_ulp"]) < 2.0
+    assert vals["exp2_special"] == "1"
