@@ -76,7 +76,7 @@ __device__ __forceinline__ double offsets_pass(const double (&v)[FIN_IT], int64_
         last = fmax(last, e[k]);
     }
     const double incl_max = block_incl_max_scan<FIN_NW>(last, red);
-    double floor_v = __shfl_up(incl_max, 1);
+    double floor_v = lane_prev(incl_max, 0.0);
     __syncthreads();
     if (lane_id() == WAVE - 1)
         red[wave_id()] = incl_max;
@@ -224,7 +224,7 @@ __device__ __forceinline__ void finalize_block(const Prob &P, int32_t step, cons
         double s2 = 0.0;
 #pragma unroll
         for (int k = 0; k < FIN_IT; ++k) {
-            const double sc = q[k].m > -INFINITY ? exp(q[k].m - M) : 0.0;
+            const double sc = q[k].m > -INFINITY ? exp_nonpos_d(q[k].m - M) : 0.0;
             v[k] = q[k].s1 * sc;
             s2 += q[k].s2 * (sc * sc);
         }
@@ -263,7 +263,7 @@ __device__ __forceinline__ void finalize_block(const Prob &P, int32_t step, cons
             ntiles,
             [&](int64_t b) {
                 const TilePartial q = part[b];
-                const double sc = q.m > -INFINITY ? exp(q.m - M) : 0.0;
+                const double sc = q.m > -INFINITY ? exp_nonpos_d(q.m - M) : 0.0;
                 s2 += q.s2 * (sc * sc);
                 return q.s1 * sc;
             },
@@ -524,14 +524,12 @@ __device__ __forceinline__ TileCdf tile_cdf(const double *__restrict__ lw, int64
     int lastpos = -1;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const double w = (l[k] > -INFINITY && mb > -INFINITY) ? exp(l[k] - mb) : 0.0;
+        const double w = mb > -INFINITY ? exp_nonpos_d(l[k] - mb) : 0.0;
         run += w;
         a[k] = run;
         lastpos = w > 0.0 ? j0 + k : lastpos;
     }
-#pragma unroll
-    for (int off = WAVE / 2; off >= 1; off >>= 1)
-        lastpos = max(lastpos, __shfl_xor(lastpos, off));
+    lastpos = wave_max_i(lastpos);
     if (lane_id() == 0)
         wave_pos[wave_id()] = lastpos;
     double total;
@@ -551,7 +549,7 @@ __device__ __forceinline__ TileCdf tile_cdf(const double *__restrict__ lw, int64
             r.S[k] = Pb;
     }
     // S of the previous particle: the neighbouring lane's last value
-    double prev = __shfl_up(r.S[ITEMS - 1], 1);
+    double prev = lane_prev(r.S[ITEMS - 1], 0.0);
     __syncthreads();
     if (lane_id() == WAVE - 1)
         wave_last[wave_id()] = r.S[ITEMS - 1];
@@ -614,7 +612,7 @@ __device__ __forceinline__ void resample_tile(const Prob &P, int64_t b, uint32_t
     }
     const double Pb = prefix[b], Pb1 = prefix[b + 1];
     const double mb = part[b].m;
-    const double sc = mb > -INFINITY ? exp(mb - M) : 0.0;
+    const double sc = mb > -INFINITY ? exp_nonpos_d(mb - M) : 0.0;
     const TileCdf cdf = tile_cdf(lw, base, len, mb, sc, Pb, Pb1, red, wave_last, wave_pos);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
@@ -840,7 +838,7 @@ __global__ __launch_bounds__(TPB) void mon_partial_kernel(
         src[k] = 0;
         if (i < n) {
             src[k] = gather ? (int64_t)anc[i] : i;
-            w[k] = reset ? 1.0 : (lw[i] > -INFINITY ? exp(lw[i] - M) : 0.0);
+            w[k] = reset ? 1.0 : exp_nonpos_d(lw[i] - M);
         }
     }
     double sw = w[0] + w[1] + w[2] + w[3];

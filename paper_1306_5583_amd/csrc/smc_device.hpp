@@ -9,6 +9,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <stdint.h>
 
 #include "smc_math.hpp"
@@ -50,6 +51,11 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
                                         Key key)
 {
     uint32_t k0 = key.k0, k1 = key.k1;
+    // The key is wave-uniform: advancing it round by round costs two scalar
+    // adds per round.  The empty asm keeps the compiler from precomputing the
+    // twenty round keys once per kernel and holding them live across every
+    // call (which exhausts the scalar registers of the larger kernels).
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         // one 32x32->64 multiply per product (v_mad_u64_u32)
@@ -91,7 +97,7 @@ __device__ __forceinline__ double2 normal2(uint4 w)
 {
     const double u1 = u53(w.x, w.y);
     const double u2 = u53(w.z, w.w);
-    const double r = sqrt(-2.0 * log_d(u1));
+    const double r = sqrt(-2.0 * log_pos_d(u1));
     double s, c;
     sincospi_d(u2 + u2, &s, &c);
     return make_double2(r * c, r * s);
@@ -158,28 +164,111 @@ __device__ inline double gamma_draw(Key key, uint32_t i, uint32_t t, uint32_t ta
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / WAVE; }
 
+// Cross-lane moves through DPP (the VALU's data-parallel operand modes): a
+// neighbour's value in a few cycles instead of a round trip through the LDS
+// crossbar.  Lanes without a source (or in rows the row mask leaves out)
+// receive `fill`.
+namespace dpp {
+enum : int {
+    ROW_SHR1 = 0x111,
+    ROW_SHR2 = 0x112,
+    ROW_SHR4 = 0x114,
+    ROW_SHR8 = 0x118,
+    WAVE_SHR1 = 0x138,
+    ROW_BCAST15 = 0x142,
+    ROW_BCAST31 = 0x143
+};
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ int mov_i(int v, int fill)
+{
+    return __builtin_amdgcn_update_dpp(fill, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double mov(double v, double fill)
+{
+    const long long b = __double_as_longlong(v), f = __double_as_longlong(fill);
+    const int lo = mov_i<CTRL, ROW_MASK>((int)b, (int)f);
+    const int hi = mov_i<CTRL, ROW_MASK>((int)(b >> 32), (int)(f >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Inclusive scan of op over the 64 lanes: shifts 1, 2, 4, 8 inside each row
+// of 16 lanes, then the row totals carried across rows by the two
+// broadcasts.  `id` is op's identity.
+template <typename Op>
+__device__ __forceinline__ double incl_scan(double v, double id, Op op)
+{
+    v = op(v, mov<ROW_SHR1>(v, id));
+    v = op(v, mov<ROW_SHR2>(v, id));
+    v = op(v, mov<ROW_SHR4>(v, id));
+    v = op(v, mov<ROW_SHR8>(v, id));
+    v = op(v, mov<ROW_BCAST15, 0xA>(v, id));
+    v = op(v, mov<ROW_BCAST31, 0xC>(v, id));
+    return v;
+}
+
+template <typename Op>
+__device__ __forceinline__ int incl_scan_i(int v, int id, Op op)
+{
+    v = op(v, mov_i<ROW_SHR1>(v, id));
+    v = op(v, mov_i<ROW_SHR2>(v, id));
+    v = op(v, mov_i<ROW_SHR4>(v, id));
+    v = op(v, mov_i<ROW_SHR8>(v, id));
+    v = op(v, mov_i<ROW_BCAST15, 0xA>(v, id));
+    v = op(v, mov_i<ROW_BCAST31, 0xC>(v, id));
+    return v;
+}
+}  // namespace dpp
+
+struct OpAdd {
+    __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct OpMax {
+    __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+struct OpMin {
+    __device__ double operator()(double a, double b) const { return fmin(a, b); }
+};
+struct OpMaxI {
+    __device__ int operator()(int a, int b) const { return a > b ? a : b; }
+};
+
+// Wave reductions (every lane receives the result: the last lane of the
+// inclusive scan, read back as a wave-uniform value).
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = WAVE / 2; off >= 1; off >>= 1)
-        v += __shfl_xor(v, off);
-    return v;
+    return dpp::readlane(dpp::incl_scan(v, 0.0, OpAdd{}), WAVE - 1);
 }
 
 __device__ __forceinline__ double wave_max(double v)
 {
-#pragma unroll
-    for (int off = WAVE / 2; off >= 1; off >>= 1)
-        v = fmax(v, __shfl_xor(v, off));
-    return v;
+    return dpp::readlane(dpp::incl_scan(v, -INFINITY, OpMax{}), WAVE - 1);
 }
 
 __device__ __forceinline__ double wave_min(double v)
 {
-#pragma unroll
-    for (int off = WAVE / 2; off >= 1; off >>= 1)
-        v = fmin(v, __shfl_xor(v, off));
-    return v;
+    return dpp::readlane(dpp::incl_scan(v, INFINITY, OpMin{}), WAVE - 1);
+}
+
+__device__ __forceinline__ int wave_max_i(int v)
+{
+    return __builtin_amdgcn_readlane(dpp::incl_scan_i(v, INT_MIN, OpMaxI{}), WAVE - 1);
+}
+
+// Value of the previous lane (lane 0 receives `fill`).
+__device__ __forceinline__ double lane_prev(double v, double fill)
+{
+    return dpp::mov<dpp::WAVE_SHR1>(v, fill);
 }
 
 // Block reductions over NW waves; `red` is __shared__ scratch of >= NW
@@ -214,17 +303,10 @@ __device__ __forceinline__ double block_max(double v, double *red)
     return s;
 }
 
-// Inclusive prefix sum across one wave (Hillis-Steele).
+// Inclusive prefix sum across one wave.
 __device__ __forceinline__ double wave_incl_scan(double v)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const double o = __shfl_up(v, d);
-        if (lane >= d)
-            v += o;
-    }
-    return v;
+    return dpp::incl_scan(v, 0.0, OpAdd{});
 }
 
 // Inclusive prefix sum across the workgroup; *total receives the sum.
@@ -254,7 +336,7 @@ template <int NW>
 __device__ __forceinline__ double block_excl_scan(double v, double *red, double *total)
 {
     const double incl = wave_incl_scan(v);
-    double excl = __shfl_up(incl, 1);
+    const double excl = lane_prev(incl, 0.0);
     __syncthreads();
     if (lane_id() == WAVE - 1)
         red[wave_id()] = incl;
@@ -274,15 +356,9 @@ __device__ __forceinline__ double block_excl_scan(double v, double *red, double 
 template <int NW>
 __device__ __forceinline__ double block_incl_max_scan(double v, double *red)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const double o = __shfl_up(v, d);
-        if (lane >= d)
-            v = fmax(v, o);
-    }
+    v = dpp::incl_scan(v, -INFINITY, OpMax{});
     __syncthreads();
-    if (lane == WAVE - 1)
+    if (lane_id() == WAVE - 1)
         red[wave_id()] = v;
     __syncthreads();
     for (int w = 0; w < wave_id(); ++w)
@@ -310,7 +386,7 @@ __device__ __forceinline__ void tile_partial(const double (&lw)[ITEMS], TilePart
     if (m > -INFINITY) {
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            const double e = lw[k] > -INFINITY ? exp(lw[k] - m) : 0.0;
+            const double e = exp_nonpos_d(lw[k] - m);
             s1 += e;
             s2 += e * e;
         }

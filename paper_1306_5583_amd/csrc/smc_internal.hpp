@@ -43,7 +43,7 @@ struct ObsModel {
         if (gaussian)
             return (c + c) - 0.5 * (rx * rx + ry * ry);
         const double q = fma(rx * rx, inv_nu, 1.0) * fma(ry * ry, inv_nu, 1.0);
-        return (c + c) - half_nu1 * log_d(q);
+        return (c + c) - half_nu1 * log_pos_d(q);
     }
 };
 

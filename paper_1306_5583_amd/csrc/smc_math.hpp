@@ -61,9 +61,8 @@ constexpr double kCosC[10] = {cos_c(0), cos_c(1), cos_c(2), cos_c(3), cos_c(4),
                               cos_c(5), cos_c(6), cos_c(7), cos_c(8), cos_c(9)};
 }  // namespace detail
 
-// Natural logarithm; exact special cases: log(0) = -inf, log(inf) = inf,
-// log(x < 0) = NaN, NaN propagates.
-__host__ __device__ inline double log_d(double x)
+// Natural logarithm of a finite x > 0 (no special-case handling).
+__host__ __device__ inline double log_pos_d(double x)
 {
     int e;
     double m = frexp(x, &e);  // x = m 2^e, m in [0.5, 1)
@@ -81,11 +80,33 @@ __host__ __device__ inline double log_d(double x)
     const double hs = s * f;           // = f - 2s up to rounding
     const double lm = f - (hs - 2.0 * s * s2 * p);
     const double de = (double)e;
-    double r = fma(de, detail::kLn2Hi, fma(de, detail::kLn2Lo, lm));
+    return fma(de, detail::kLn2Hi, fma(de, detail::kLn2Lo, lm));
+}
+
+// Natural logarithm; exact special cases: log(0) = -inf, log(inf) = inf,
+// log(x < 0) = NaN, NaN propagates.
+__host__ __device__ inline double log_d(double x)
+{
+    double r = log_pos_d(x);
     r = (x == 0.0) ? -INFINITY : r;
     r = (x < 0.0 || x != x) ? __builtin_nan("") : r;
     r = (x == INFINITY) ? INFINITY : r;
     return r;
+}
+
+// Exponential of x <= 0 (weights relative to a maximum): x below -1100
+// and -inf give 0 through gradual underflow; NaN is not handled.
+__host__ __device__ inline double exp_nonpos_d(double x)
+{
+    const double xc = fmax(x, -1100.0);
+    const double k = rint(xc * detail::kLog2e);
+    double r = fma(-k, detail::kLn2Hi, xc);
+    r = fma(-k, detail::kLn2Lo, r);
+    double p = detail::kExpC[13];
+#pragma unroll
+    for (int j = 12; j >= 0; --j)
+        p = fma(p, r, detail::kExpC[j]);
+    return ldexp(p, (int)k);
 }
 
 // Exponential; exp(-inf) = 0, exp(x < -745.2) = 0 (through gradual

@@ -122,7 +122,7 @@ __device__ __forceinline__ void pf_move_tile(const Prob &P, const T *__restrict_
         const T px = xin[src], py = xin[n + src], vx = xin[2 * n + src], vy = xin[3 * n + src];
         const double lw_in = (FUSE && !reset) || (MON && !reset) ? lw[i] : 0.0;
         if (MON) {
-            const double w = reset ? 1.0 : (lw_in > -INFINITY ? exp(lw_in - M) : 0.0);
+            const double w = reset ? 1.0 : exp_nonpos_d(lw_in - M);
             if (w != 0.0) {
                 ms[0] += w;
                 ms[1] += w * (double)px;
