@@ -286,6 +286,16 @@ smc_status smc_draw_words(uint64_t seed, uint32_t step, uint32_t tag, uint32_t c
  * Restrictions: systematic resampling, double-precision tracking state,
  * the same move kind and sweep count for all mixture samplers.
  * ------------------------------------------------------------------------ */
+/* Timing of the sweep's dominant kernel (the tracking filter's move
+ * kernel) by events carried in the kernel's own dispatch, so the stream
+ * receives no extra packets: the next `count` move launches of this context
+ * are timed (count = 0 disarms).  smc_profile_read waits for them and writes
+ * up to `capacity` durations in milliseconds, in launch order; *written
+ * receives how many.  Host-side bookkeeping only; events are owned by the
+ * context. */
+smc_status smc_profile_start(smc_ctx *ctx, int32_t count);
+smc_status smc_profile_read(smc_ctx *ctx, float *ms, int32_t capacity, int32_t *written);
+
 typedef struct smc_batch smc_batch;
 
 typedef struct smc_batch_problem {

@@ -119,6 +119,8 @@ def load() -> ctypes.CDLL:
         "smc_last_error": (ctypes.c_char_p, [_vp]),
         "smc_gmm_loglik_grad": (st, [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp, _vp, _vp]),
         "smc_draw_words": (st, [_u64, _u32, _u32, _u32, _u32, _i64, _vp, _vp]),
+        "smc_profile_start": (st, [_vp, _i32]),
+        "smc_profile_read": (st, [_vp, P(ctypes.c_float), _i32, P(_i32)]),
         "smc_batch_table_size": (st, [P(smc_batch_problem), _i32, P(ctypes.c_size_t)]),
         "smc_batch_create": (st, [P(smc_batch_problem), _i32, _vp, ctypes.c_size_t, _vp,
                                   P(_vp)]),
@@ -145,7 +147,7 @@ def exported_symbols():
             "smc_destroy", "smc_set_stream", "smc_init", "smc_move", "smc_reweight", "smc_ess",
             "smc_resample", "smc_monitor", "smc_gather", "smc_current_state",
             "smc_read_scalars", "smc_check", "smc_last_error", "smc_gmm_loglik_grad",
-            "smc_draw_words", "smc_batch_table_size", "smc_batch_create", "smc_batch_destroy",
+            "smc_draw_words", "smc_profile_start", "smc_profile_read", "smc_batch_table_size", "smc_batch_create", "smc_batch_destroy",
             "smc_batch_autotune", "smc_batch_waves", "smc_batch_init", "smc_batch_step",
             "smc_batch_capture", "smc_batch_replay", "smc_batch_check", "smc_batch_last_error"]
 
@@ -278,6 +280,17 @@ def smc_gmm_loglik_grad(mu_ptr, eta_ptr, z_ptr, n, K, y_ptr, n_data, ll_ptr, gra
 def smc_draw_words(seed, step, tag, call, problem, n, out_ptr, stream_handle):
     _check(load().smc_draw_words(seed, step, tag, call, problem, n, _vp(out_ptr),
                                  _vp(stream_handle)), "smc_draw_words")
+
+
+def smc_profile_start(ctx, count):
+    _check(load().smc_profile_start(ctx, count), "smc_profile_start", ctx)
+
+
+def smc_profile_read(ctx, capacity):
+    out = (ctypes.c_float * max(capacity, 1))()
+    w = _i32()
+    _check(load().smc_profile_read(ctx, out, capacity, ctypes.byref(w)), "smc_profile_read", ctx)
+    return list(out[:w.value])
 
 
 # ------------------------------------------------------------------ batch ---

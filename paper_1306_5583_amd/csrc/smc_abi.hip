@@ -334,9 +334,57 @@ smc_status smc_create(const smc_config *cfg, const smc_buffers *buf, void *hip_s
     return SMC_OK;
 }
 
+static void drop_profile_events(Ctx &c)
+{
+    for (hipEvent_t e : c.prof_ev)
+        (void)hipEventDestroy(e);
+    c.prof_ev.clear();
+    c.prof_next = c.prof_armed = 0;
+}
+
 smc_status smc_destroy(smc_ctx *ctx)
 {
+    if (ctx)
+        drop_profile_events(ctx->c);
     delete ctx;
+    return SMC_OK;
+}
+
+smc_status smc_profile_start(smc_ctx *ctx, int32_t count)
+{
+    if (!ctx || count < 0 || count > (1 << 20))
+        return SMC_ERR_INVALID_ARG;
+    Ctx &c = ctx->c;
+    drop_profile_events(c);
+    c.prof_ev.resize(2 * (size_t)count, nullptr);
+    for (int32_t k = 0; k < 2 * count; ++k) {
+        const hipError_t e = hipEventCreate(&c.prof_ev[k]);
+        if (e != hipSuccess) {
+            c.prof_ev.resize(k);
+            drop_profile_events(c);
+            return fail(c, SMC_ERR_DEVICE, std::string("smc_profile_start: ") +
+                                               hipGetErrorString(e));
+        }
+    }
+    c.prof_armed = count;
+    return SMC_OK;
+}
+
+smc_status smc_profile_read(smc_ctx *ctx, float *ms, int32_t capacity, int32_t *written)
+{
+    if (!ctx || !written || (capacity > 0 && !ms))
+        return SMC_ERR_INVALID_ARG;
+    Ctx &c = ctx->c;
+    const int32_t m = c.prof_next < capacity ? c.prof_next : capacity;
+    for (int32_t k = 0; k < m; ++k) {
+        hipError_t e = hipEventSynchronize(c.prof_ev[2 * k + 1]);
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms[k], c.prof_ev[2 * k], c.prof_ev[2 * k + 1]);
+        if (e != hipSuccess)
+            return fail(c, SMC_ERR_DEVICE, std::string("smc_profile_read: ") +
+                                               hipGetErrorString(e));
+    }
+    *written = m;
     return SMC_OK;
 }
 

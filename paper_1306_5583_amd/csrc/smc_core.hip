@@ -50,9 +50,9 @@ hipError_t launch_reset_scalars(Ctx &c)
 // give the same outputs.  `val(b)` is called exactly once per b, in
 // increasing b for each lane.
 // ---------------------------------------------------------------------------
-constexpr int FIN_TPB = 1024;
+constexpr int FIN_TPB = 512;
 constexpr int FIN_NW = FIN_TPB / WAVE;
-constexpr int FIN_IT = 4;
+constexpr int FIN_IT = 8;
 constexpr int FIN_PASS = FIN_TPB * FIN_IT;
 
 // One pass: lane values v[] for b0 .. b0+FIN_IT-1; returns the new carry.
@@ -110,36 +110,11 @@ __device__ double tile_offsets(int64_t count, F val, double *out, double *red)
     return carry;
 }
 
-// Workgroup sums of R values at once (one pair of barriers).
-template <int NW, int R>
-__device__ __forceinline__ void block_sum_multi(double (&v)[R], double *red /* NW*R */)
-{
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        v[r] = wave_sum(v[r]);
-    __syncthreads();
-    if (lane_id() == 0) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            red[wave_id() * R + r] = v[r];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        double a = red[r];
-        for (int w = 1; w < NW; ++w)
-            a += red[w * R + r];
-        v[r] = a;
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Normalisation (single workgroup): global max M, tile offsets of the
-// cumulative weights, S1 = sum exp(lw - M), S2 = sum exp(2 (lw - M)),
-// L = M + log S1, L2 = 2M + log S2, ESS = exp(2L - L2), dlogZ = L - L_prev,
-// decision ESS < tau N (tau >= 1 always, tau <= 0 never).  When a move
-// carried the monitor partials of the previous step (mon_step >= 0), their
-// importance-sampling estimates are completed here as well.
+// Normalisation and the completion of monitor partials.  A move can carry
+// the monitor partials of the previous step (per tile: sum w and sum w x
+// for each monitored row); their importance-sampling estimates are
+// completed alongside the next normalisation.
 // ---------------------------------------------------------------------------
 struct MonDest {
     int32_t step;     // history row, or -1 when no monitor partials are pending
@@ -186,66 +161,88 @@ __device__ void mon_combine(const double *__restrict__ mon, int64_t ntiles, cons
 
 constexpr int FIN_MON_ROWS = 4;  // rows a move can carry (the tracking state)
 
-__device__ __forceinline__ void finalize_block(const Prob &P, int32_t step, const MonDest &md)
+// Single pass over at most FIN_PASS tile partials: lane t owns FIN_IT
+// consecutive tiles.  The cumulative offsets are the lane's running sums on
+// top of the workgroup scan of the lane totals, each clamped to the lane's
+// inclusive value, which is exactly the next lane's starting offset (and the
+// next wave's: the wave totals are summed in order), so the offsets never
+// decrease.  The sum of squares rides on the same barrier pair.
+__device__ __forceinline__ void normalise_one_pass(const TilePartial *__restrict__ part,
+                                                   int64_t ntiles, double *__restrict__ prefix,
+                                                   double *red, double *M_out, double *S1_out,
+                                                   double *S2_out)
 {
-    __shared__ double red[FIN_NW * (FIN_MON_ROWS + 2)];
-    __shared__ double col[MON_STRIDE];
+    const int tid = threadIdx.x;
+    const int64_t b0 = (int64_t)tid * FIN_IT;
+    TilePartial q[FIN_IT];
+#pragma unroll
+    for (int k = 0; k < FIN_IT; ++k)
+        q[k] = b0 + k < ntiles ? part[b0 + k] : TilePartial{-INFINITY, 0.0, 0.0, 0.0};
+    double m = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < FIN_IT; ++k)
+        m = fmax(m, q[k].m);
+    const double M = block_max<FIN_NW>(m, red);
+    double e[FIN_IT];
+    double run = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < FIN_IT; ++k) {
+        const double sc = q[k].m > -INFINITY ? exp_nonpos_d(q[k].m - M) : 0.0;
+        e[k] = run;
+        run += q[k].s1 * sc;
+        s2 += q[k].s2 * (sc * sc);
+    }
+    const double incl = wave_incl_scan(run);
+    const double excl = lane_prev(incl, 0.0);
+    const double s2w = wave_sum(s2);
+    __syncthreads();  // red is reused from block_max
+    if (lane_id() == WAVE - 1) {
+        red[wave_id()] = incl;
+        red[FIN_NW + wave_id()] = s2w;
+    }
+    __syncthreads();
+    double before = 0.0, total = 0.0, S2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < FIN_NW; ++w) {
+        if (w < wave_id())
+            before += red[w];
+        total += red[w];
+        S2 += red[FIN_NW + w];
+    }
+    const double lo = lane_id() == 0 ? before : before + excl;
+    const double hi = before + incl;
+#pragma unroll
+    for (int k = 0; k < FIN_IT; ++k)
+        if (b0 + k < ntiles)
+            prefix[b0 + k] = fmin(lo + e[k], hi);
+    if (tid == 0)
+        prefix[ntiles] = total;
+    *M_out = M;
+    *S1_out = total;
+    *S2_out = S2;
+}
+
+// Normalisation (one workgroup): global max M, tile offsets of the
+// cumulative weights, S1 = sum exp(lw - M), S2 = sum exp(2 (lw - M)),
+// L = M + log S1, L2 = 2M + log S2, ESS = exp(2L - L2), dlogZ = L - L_prev,
+// decision ESS < tau N (tau >= 1 always, tau <= 0 never).
+__device__ __forceinline__ void normalise_block(const Prob &P, int32_t step)
+{
+    __shared__ double red[2 * FIN_NW];
     const TilePartial *__restrict__ part = P.partials;
     const int64_t ntiles = P.ntiles, n = P.n;
-    const double threshold = P.threshold;
     double *__restrict__ prefix = P.prefix;
     double *__restrict__ scalars = P.scalars;
-    double *__restrict__ hist = P.hist;
-    const int64_t hist_len = P.hist_len;
-    int32_t *__restrict__ counters = P.counters;
-    const double *__restrict__ mon = P.mon;
     const int tid = threadIdx.x;
+    // the previous L and log Z, fetched while the partials arrive
+    double Lprev = 0.0, logz_prev = 0.0;
+    if (tid == 0) {
+        Lprev = scalars[SMC_S_L];
+        logz_prev = scalars[SMC_S_LOGZ];
+    }
     double M, S1, S2;
     if (ntiles <= FIN_PASS) {
-        // one pass: every load of this lane is issued up front
-        const int64_t b0 = (int64_t)tid * FIN_IT;
-        TilePartial q[FIN_IT];
-        double mo[FIN_MON_ROWS + 1][FIN_IT];
-#pragma unroll
-        for (int k = 0; k < FIN_IT; ++k) {
-            const bool ok = b0 + k < ntiles;
-            q[k] = ok ? part[b0 + k] : TilePartial{-INFINITY, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int r = 0; r <= FIN_MON_ROWS; ++r)
-                mo[r][k] = (ok && md.step >= 0 && r <= md.rows) ? mon[(int64_t)r * ntiles + b0 + k]
-                                                                : 0.0;
-        }
-        double m = -INFINITY;
-#pragma unroll
-        for (int k = 0; k < FIN_IT; ++k)
-            m = fmax(m, q[k].m);
-        M = block_max<FIN_NW>(m, red);
-        double v[FIN_IT];
-        double s2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < FIN_IT; ++k) {
-            const double sc = q[k].m > -INFINITY ? exp_nonpos_d(q[k].m - M) : 0.0;
-            v[k] = q[k].s1 * sc;
-            s2 += q[k].s2 * (sc * sc);
-        }
-        S1 = offsets_pass(v, b0, ntiles, 0.0, prefix, red);
-        if (tid == 0)
-            prefix[ntiles] = S1;
-        double acc[FIN_MON_ROWS + 2];
-        acc[0] = s2;
-#pragma unroll
-        for (int r = 0; r <= FIN_MON_ROWS; ++r)
-            acc[1 + r] = ((mo[r][0] + mo[r][1]) + mo[r][2]) + mo[r][3];
-        block_sum_multi<FIN_NW, FIN_MON_ROWS + 2>(acc, red);
-        S2 = acc[0];
-        if (md.step >= 0 && tid < md.rows) {
-            const double est = acc[2 + tid] / acc[1];
-            if (md.out)
-                md.out[tid] = est;
-            if (hist && md.step < hist_len && tid >= md.rows - md.hist_ncols)
-                hist[(int64_t)md.step * SMC_HIST_COLS + md.hist_col +
-                     (tid - (md.rows - md.hist_ncols))] = est;
-        }
+        normalise_one_pass(part, ntiles, prefix, red, &M, &S1, &S2);
     } else {
         double m = -INFINITY;
         for (int64_t b = (int64_t)tid * FIN_IT; b < ntiles; b += FIN_PASS) {
@@ -269,16 +266,14 @@ __device__ __forceinline__ void finalize_block(const Prob &P, int32_t step, cons
             },
             prefix, red);
         S2 = block_sum<FIN_NW>(s2, red);
-        if (md.step >= 0)
-            mon_combine<FIN_TPB>(mon, ntiles, md, hist, hist_len, red, col);
     }
     if (tid == 0) {
+        const double threshold = P.threshold;
         const double L = M + log(S1);
         const double L2 = 2.0 * M + log(S2);
         const double ess = exp(2.0 * L - L2);
-        const double Lprev = scalars[SMC_S_L];
         const double dlogz = L - Lprev;
-        const double logz = scalars[SMC_S_LOGZ] + dlogz;
+        const double logz = logz_prev + dlogz;
         int flag;
         if (threshold >= 1.0)
             flag = 1;
@@ -287,7 +282,7 @@ __device__ __forceinline__ void finalize_block(const Prob &P, int32_t step, cons
         else
             flag = ess < threshold * (double)n;
         if (!(S1 > 0.0) || !isfinite(S1) || !isfinite(M)) {
-            atomicOr(&counters[CNT_ERR], SMC_DEVERR_NONFINITE);
+            atomicOr(&P.counters[CNT_ERR], SMC_DEVERR_NONFINITE);
             flag = 0;
         }
         scalars[SMC_S_L] = L;
@@ -298,8 +293,8 @@ __device__ __forceinline__ void finalize_block(const Prob &P, int32_t step, cons
         scalars[SMC_S_FLAG] = (double)flag;
         scalars[SMC_S_M] = M;
         scalars[SMC_S_STOT] = S1;
-        if (hist && step >= 0 && step < hist_len) {
-            double *h = hist + (int64_t)step * SMC_HIST_COLS;
+        if (P.hist && step >= 0 && step < P.hist_len) {
+            double *h = P.hist + (int64_t)step * SMC_HIST_COLS;
             h[SMC_H_ESS] = ess;
             h[SMC_H_FLAG] = (double)flag;
             h[SMC_H_DLOGZ] = dlogz;
@@ -309,32 +304,53 @@ __device__ __forceinline__ void finalize_block(const Prob &P, int32_t step, cons
     }
 }
 
-__global__ __launch_bounds__(FIN_TPB) void finalize_kernel(Prob P, int32_t step, MonDest md)
+// Completion of monitor partials carried by a move (importance-sampling
+// estimates of the previous step), independent of the normalisation.
+__device__ __forceinline__ void monitor_block(const Prob &P, const MonDest &md)
 {
-    finalize_block(P, step, md);
+    __shared__ double red[FIN_NW];
+    __shared__ double col[MON_STRIDE];
+    mon_combine<FIN_TPB>(P.mon, P.ntiles, md, P.hist, P.hist_len, red, col);
 }
 
-// Batched normalisation: one workgroup per problem; tracking problems also
-// complete the monitor of the previous step carried by the batched move.
+// Workgroup 0 normalises; workgroup 1 (launched only when monitor partials
+// are pending) completes the monitor at the same time.
+__global__ __launch_bounds__(FIN_TPB) void finalize_kernel(Prob P, int32_t step, MonDest md)
+{
+    if (blockIdx.x == 0)
+        normalise_block(P, step);
+    else
+        monitor_block(P, md);
+}
+
+// Batched normalisation: two workgroups per problem, the second completing
+// (for tracking problems) the monitor of the previous step carried by the
+// batched move.
 __global__ __launch_bounds__(FIN_TPB) void finalize_batch_kernel(const Prob *__restrict__ probs,
                                                                  const int32_t *__restrict__ step)
 {
-    const Prob &P = probs[blockIdx.x];
+    const Prob &P = probs[blockIdx.x >> 1];
     const int32_t t = *step;
+    if ((blockIdx.x & 1) == 0) {
+        normalise_block(P, t);
+        return;
+    }
+    if (P.kind != SMC_MODEL_CV_TRACK || t < 1)
+        return;
     MonDest md;
     md.out = nullptr;
     md.rows = FIN_MON_ROWS;
     md.hist_col = SMC_H_MON;
     md.hist_ncols = FIN_MON_ROWS;
-    md.step = (P.kind == SMC_MODEL_CV_TRACK && t >= 1) ? t - 1 : -1;
-    finalize_block(P, t, md);
+    md.step = t - 1;
+    monitor_block(P, md);
 }
 
 hipError_t launch_finalize_batch(const Prob *probs, int32_t nprob, const int32_t *step,
                                  hipStream_t s)
 {
-    hipLaunchKernelGGL(finalize_batch_kernel, dim3((unsigned)nprob), dim3(FIN_TPB), 0, s, probs,
-                       step);
+    hipLaunchKernelGGL(finalize_batch_kernel, dim3(2 * (unsigned)nprob), dim3(FIN_TPB), 0, s,
+                       probs, step);
     return hipGetLastError();
 }
 
@@ -396,8 +412,8 @@ hipError_t launch_finalize(Ctx &c, int32_t step)
     MonDest md = mon_dest(c, c.mon_pending_step, c.mon_pending_rows, c.mon_pending_out);
     if (c.mon_pending_step < 0)
         md.step = -1;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_TPB), 0, c.stream, make_prob(c), step,
-                       md);
+    hipLaunchKernelGGL(finalize_kernel, dim3(md.step >= 0 ? 2 : 1), dim3(FIN_TPB), 0, c.stream,
+                       make_prob(c), step, md);
     c.mon_pending_step = -1;
     return hipGetLastError();
 }

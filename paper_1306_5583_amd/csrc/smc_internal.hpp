@@ -2,11 +2,13 @@
 // translation units of libsmc (not part of the public ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/smc.h"
 #include "smc_device.hpp"
@@ -113,6 +115,22 @@ struct Ctx {
     int mon_pending_rows = 0;
     double *mon_pending_out = nullptr;
     std::string last_error;
+    // Dispatch-carried timing of the move kernel: pairs of events, the next
+    // unused pair index and how many pairs are armed.
+    std::vector<hipEvent_t> prof_ev;
+    int prof_next = 0;
+    int prof_armed = 0;
+
+    // Next armed (start, stop) pair, if any.
+    bool prof_take(hipEvent_t *a, hipEvent_t *b)
+    {
+        if (prof_next >= prof_armed)
+            return false;
+        *a = prof_ev[2 * prof_next];
+        *b = prof_ev[2 * prof_next + 1];
+        ++prof_next;
+        return true;
+    }
 
     void *state_ptr() const { return cur == 0 ? buf.state : buf.state_alt; }
     void *other_ptr() const { return cur == 0 ? buf.state_alt : buf.state; }

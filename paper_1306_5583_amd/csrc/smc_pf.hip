@@ -184,9 +184,15 @@ static void launch_move_t(Ctx &c, int32_t step, int32_t obs_index, bool gather_c
                           bool reset_check)
 {
     const Prob P = make_prob(c);
-    hipLaunchKernelGGL((pf_move_kernel<T, FUSE, MON>), dim3((unsigned)c.ntiles), dim3(TPB), 0,
-                       c.stream, P, (uint32_t)step, obs_index, (int)gather_check,
-                       (int)reset_check);
+    hipEvent_t e0, e1;
+    if (c.prof_take(&e0, &e1))
+        hipExtLaunchKernelGGL((pf_move_kernel<T, FUSE, MON>), dim3((unsigned)c.ntiles), dim3(TPB),
+                              0, c.stream, e0, e1, 0, P, (uint32_t)step, obs_index,
+                              (int)gather_check, (int)reset_check);
+    else
+        hipLaunchKernelGGL((pf_move_kernel<T, FUSE, MON>), dim3((unsigned)c.ntiles), dim3(TPB),
+                           0, c.stream, P, (uint32_t)step, obs_index, (int)gather_check,
+                           (int)reset_check);
 }
 
 hipError_t launch_pf_move(Ctx &c, int32_t step, int32_t obs_index, bool fuse, bool gather_check,

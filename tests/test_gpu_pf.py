@@ -296,3 +296,20 @@ def test_out_of_order_calls_rejected(lib):
     with pytest.raises(L.SmcError) as e:
         L.smc_move(pf.ctx, 1, m)
     assert e.value.status == L.SMC_ERR_INVALID_ARG
+
+
+def test_move_kernel_profile_events(lib):
+    # dispatch-carried timing of the move kernel: one duration per timed launch
+    pkg, L = lib
+    _, y = synth.pf_trajectory(12, 3)
+    pf = pkg.ParticleFilter(1 << 16, y, seed=2)
+    pf.init()
+    L.smc_profile_start(pf.ctx, 5)
+    for t in range(1, 12):
+        pf.step(t)
+    pf.finish()
+    ms = L.smc_profile_read(pf.ctx, 16)
+    assert len(ms) == 5 and all(0.0 < v < 50.0 for v in ms)
+    L.smc_profile_start(pf.ctx, 0)
+    assert L.smc_profile_read(pf.ctx, 4) == []
+    pf.check()
