@@ -1,3 +1,4 @@
+
 /* Declarations shared by the oracle's own C files (test infrastructure only;
  * never included by the GPU library). */
 #ifndef ORACLE_INTERNAL_H

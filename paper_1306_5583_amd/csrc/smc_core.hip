@@ -704,6 +704,137 @@ __device__ __forceinline__ void resample_tile(const Prob &P, int64_t b, uint32_t
     }
 }
 
+// Systematic resampling of one tile by replication numbers (Section 2.1:
+// particle j copied R_j times, sum N).  Particle j owns the slots
+// [c(S_{j-1}), c(S_j)) with c(x) = min(N, max(0, ceil(x N / S - U))) (one
+// fused multiply-add), the number of ordered uniforms (i + U) / N below
+// x / S, so R_j = c(S_j) - c(S_{j-1}) and every lane finds the ranges of its
+// own particles directly.  The tile's slots are then
+// filled through LDS in chunks of RS_UCAP: each particle with a non-empty
+// range marks the range's first slot with its index and an inclusive
+// max-scan spreads it over the range, which keeps the stores coalesced and
+// the work even however the slots fall on the particles.
+__device__ __forceinline__ void resample_sys_tile(const Prob &P, int64_t b, uint32_t t,
+                                                  int32_t force)
+{
+    constexpr int QPT = RS_UCAP / TPB;  // chunk slots per lane
+    const double *__restrict__ lw = P.lw;
+    const double *__restrict__ prefix = P.prefix;
+    const int64_t n = P.n, ntiles = P.ntiles;
+    double *__restrict__ scalars = P.scalars;
+    int32_t *__restrict__ anc = P.anc;
+    __shared__ double red[NWAVES];
+    __shared__ double wave_last[NWAVES];
+    __shared__ int wave_pos[NWAVES];
+    __shared__ int wave_end[NWAVES];
+    __shared__ int wave_max[NWAVES];
+    __shared__ int owner[RS_UCAP];
+    __shared__ long long tile_lo;
+    const int tid = threadIdx.x;
+    const bool go = force != 0 || scalars[SMC_S_FLAG] != 0.0;
+    const uint4 wU = draw(P.key, 0, t, TAG_RESAMPLE, 0, P.problem_id);
+    const double U = u53(wU.x, wU.y);
+    if (!go) {
+        if (b == 0 && tid == 0)
+            scalars[SMC_S_RESAMPLED] = 0.0;
+        return;
+    }
+    const int64_t base = b * TILE;
+    const int len = (int)min((int64_t)TILE, n - base);
+    const double M = scalars[SMC_S_M];
+    const double stot = prefix[ntiles];
+    if (!(stot > 0.0) || !isfinite(stot) || !isfinite(M)) {
+        if (b == 0 && tid == 0) {
+            atomicOr(&P.counters[CNT_ERR], SMC_DEVERR_ZERO_WEIGHTS);
+            scalars[SMC_S_RESAMPLED] = 0.0;
+        }
+        return;
+    }
+    const double Pb = prefix[b], Pb1 = prefix[b + 1];
+    const double mb = P.partials[b].m;
+    const double sc = mb > -INFINITY ? exp_nonpos_d(mb - M) : 0.0;
+    const TileCdf cdf = tile_cdf(lw, base, len, mb, sc, Pb, Pb1, red, wave_last, wave_pos);
+    const double nd = (double)n;
+    const double r = nd / stot;
+    // c(x) = min(N, max(0, ceil(x N / S - U))): the number of uniforms
+    // (i + U) / N below x / S, in closed form
+    auto count = [&](double x) -> int64_t {
+        const double c = ceil(fma(x, r, -U));
+        return !(c > 0.0) ? 0 : (c >= nd ? n : (int64_t)c);
+    };
+    // the tile holding the last positive weight also takes the slots whose
+    // uniform reaches the total (from its last positive particle on)
+    const bool has_last = Pb < stot && Pb1 >= stot;
+    const int j0 = ITEMS * tid;
+    int ce[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+        ce[k] = (int)((has_last && j0 + k >= cdf.lastpos) ? n : count(cdf.S[k]));
+    if (tid == 0)
+        tile_lo = count(Pb);
+    int cs0 = dpp::mov_i<dpp::WAVE_SHR1>(ce[ITEMS - 1], 0);
+    if (lane_id() == WAVE - 1)
+        wave_end[wave_id()] = ce[ITEMS - 1];
+    __syncthreads();
+    if (lane_id() == 0)
+        cs0 = wave_id() == 0 ? (int)tile_lo : wave_end[wave_id() - 1];
+    const int64_t lo = tile_lo, hi = wave_end[NWAVES - 1];
+    int carry = -1;
+    for (int64_t c0 = lo; c0 < hi; c0 += RS_UCAP) {
+        const int cn = (int)min((int64_t)RS_UCAP, hi - c0);
+#pragma unroll
+        for (int i = 0; i < QPT; ++i)
+            owner[tid + i * TPB] = -1;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int st = k == 0 ? cs0 : ce[k - 1];
+            if (ce[k] > st && st >= c0 && st < c0 + cn)
+                owner[st - c0] = j0 + k;
+        }
+        __syncthreads();
+        // inclusive max-scan of owner[0, cn): QPT consecutive slots per lane
+        int v[QPT];
+        int run = -1;
+#pragma unroll
+        for (int i = 0; i < QPT; ++i) {
+            run = max(run, owner[tid * QPT + i]);
+            v[i] = run;
+        }
+        const int incl = dpp::incl_scan_i(run, -1, OpMaxI{});
+        int before = dpp::mov_i<dpp::WAVE_SHR1>(incl, -1);
+        if (lane_id() == WAVE - 1)
+            wave_max[wave_id()] = incl;
+        __syncthreads();
+        for (int w = 0; w < wave_id(); ++w)
+            before = max(before, wave_max[w]);
+        before = max(before, carry);
+        int last = carry;
+#pragma unroll
+        for (int w = 0; w < NWAVES; ++w)
+            last = max(last, wave_max[w]);
+#pragma unroll
+        for (int i = 0; i < QPT; ++i)
+            owner[tid * QPT + i] = max(v[i], before);
+        __syncthreads();
+        for (int q = tid; q < cn; q += TPB)
+            anc[c0 + q] = (int32_t)(base + owner[q]);
+        carry = last;
+        __syncthreads();
+    }
+    if (b == 0 && tid == 0) {
+        scalars[SMC_S_RESAMPLED] = 1.0;
+        scalars[SMC_S_LPRE] = scalars[SMC_S_L];
+        scalars[SMC_S_L] = log(nd);
+        scalars[SMC_S_U] = U;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void resample_sys_kernel(Prob P, uint32_t t, int32_t force)
+{
+    resample_sys_tile(P, blockIdx.x, t, force);
+}
+
 template <int SCHEME>
 __global__ __launch_bounds__(TPB) void resample_merge_kernel(Prob P, uint32_t t, int32_t force,
                                                              const double *__restrict__ G)
@@ -717,7 +848,7 @@ __global__ __launch_bounds__(TPB) void resample_batch_kernel(const Prob *__restr
                                                              const int32_t *__restrict__ step)
 {
     const int2 pm = map[blockIdx.x];
-    resample_tile<SMC_RS_SYSTEMATIC>(probs[pm.x], pm.y, (uint32_t)*step, 0, nullptr);
+    resample_sys_tile(probs[pm.x], pm.y, (uint32_t)*step, 0);
 }
 
 // --- multinomial: cumulative sums G of N+1 exponentials -------------------
@@ -795,8 +926,8 @@ hipError_t launch_resample(Ctx &c, int32_t step, int32_t force)
     const dim3 grid((unsigned)c.ntiles);
     switch (c.cfg.scheme) {
     case SMC_RS_SYSTEMATIC:
-        hipLaunchKernelGGL(resample_merge_kernel<SMC_RS_SYSTEMATIC>, grid, dim3(TPB), 0, c.stream,
-                           P, (uint32_t)step, force, (const double *)nullptr);
+        hipLaunchKernelGGL(resample_sys_kernel, grid, dim3(TPB), 0, c.stream, P, (uint32_t)step,
+                           force);
         break;
     case SMC_RS_STRATIFIED:
         hipLaunchKernelGGL(resample_merge_kernel<SMC_RS_STRATIFIED>, grid, dim3(TPB), 0, c.stream,

@@ -182,3 +182,37 @@ def test_ties_go_right_and_clamp(orc):
     lw2[-3:] = -np.inf          # last positive weight is index n-4
     anc2, S2 = orc.ancestors(lw2, np.full(n, 1.0))
     assert np.all(anc2 == n - 4)
+
+
+def test_systematic_counts_closed_form_exact(orc):
+    # R_j = ceil(N S_j / S - U) - ceil(N S_{j-1} / S - U) in exact rational
+    # arithmetic on the oracle's own cumulative weights (slots past the last
+    # count go to the last positive weight); only counts whose argument lies
+    # within 1e-12 of an integer may round the other way
+    from fractions import Fraction
+    rng = np.random.default_rng(21)
+    for trial in range(12):
+        n = int(rng.integers(3, 400))
+        lw = rng.normal(0, 2.0, n)
+        lw[rng.random(n) < 0.2] = -np.inf
+        if not np.isfinite(lw).any():
+            lw[0] = 0.0
+        anc, S, u = orc.resample("systematic", 99, trial, lw)
+        w = orc.draw_words(99, 0, trial, 7, 0)     # the step's systematic U
+        U = Fraction(orc.u53(w[0], w[1]))
+        tot = Fraction(float(S[-1]))
+        R = _counts(anc, n)
+        prev = 0
+        near = set()
+        for j in range(n):
+            x = Fraction(float(S[j])) * n / tot - U
+            c = min(n, max(0, -((-x.numerator) // x.denominator)))
+            if abs(float(x) - round(float(x))) < 1e-12 * n:
+                near.add(j)
+            exp_r = c - prev
+            if j not in near and (j == 0 or j - 1 not in near):
+                pos = np.nonzero(np.isfinite(lw))[0]
+                if j != pos[-1]:
+                    assert R[j] == exp_r, (trial, j, R[j], exp_r)
+            prev = c
+        assert R.sum() == n
