@@ -1,22 +1,30 @@
 """Benchmark of the SMC sweep on one MI355X.
 
-Workload: the 2-D tracking particle filter at scale -- N = 2^22 particles,
-T = 200 observations of a seeded synthetic trajectory, FP64 state and
-log-weights, systematic resampling when ESS < N/2.  A "step" is one full
-iteration of the sweep: fused move + incremental weight, normalisation (ESS,
-log Z, decision), resampling, monitor.  The value is particle-updates per
-second (N x timed steps / timed seconds) with every input resident in HBM.
+Default workload (--workload pf): the 2-D tracking particle filter at scale
+-- N = 2^22 particles, T = 200 observations of a seeded synthetic
+trajectory, FP64 state and log-weights, systematic resampling when
+ESS < N/2.  A "step" is one full iteration of the sweep: fused move +
+incremental weight, normalisation (ESS, log Z, decision), resampling,
+monitor.  The value is particle-updates per second (N x timed steps / timed
+seconds) with every input resident in HBM.
 
-The JSON line also carries the roofline of the dominant kernel (the fused
-move + weight sweep, HBM-bound: its algorithmic bytes per launch over its
-average duration from HIP events on the launch stream) and the CPU oracle
-timed on a bounded sample of the same workload.
+The JSON line carries the roofline of the dominant kernel (the fused move +
+weight sweep, HBM-bound: its algorithmic bytes per launch over its average
+duration, timed by events carried in each launch's own dispatch), the HBM
+traffic the rocprofv3 counters measured for it (from the committed counter
+summary, when it was taken on the current kernel source), and the CPU
+oracle timed on a bounded sample of the same workload.
+
+Other workloads: --workload gmm-c2 / gmm-c3 (the tempered mixture sampler,
+FP64 vector-ALU bound), batch (many filters and samplers in one graph per
+step), copy (a plain device copy, the calibration kernel for the traffic
+counters and a measured HBM ceiling).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -27,25 +35,59 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
 METRIC = "particle-updates/s"
+CSRC = os.path.join(ROOT, "paper_1306_5583_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+# sources whose change invalidates a stored counter measurement
+PF_MOVE_SOURCES = ["smc_pf.hip", "smc_device.hpp", "smc_math.hpp", "smc_internal.hpp"]
+GMM_BLOCK_SOURCES = ["smc_gmm_impl.hpp", "smc_device.hpp", "smc_math.hpp", "smc_internal.hpp"]
 
 
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="pf",
+                    choices=["pf", "gmm-c2", "gmm-c3", "batch", "copy"])
     ap.add_argument("--steps", type=int, default=189)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=1 << 22)
     ap.add_argument("--T", type=int, default=200)
     ap.add_argument("--scheme", default="systematic")
     ap.add_argument("--fp32-state", action="store_true")
+    ap.add_argument("--move", default=None, help="gmm: rw or mala (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1 << 20)
     ap.add_argument("--cpu-sample-T", type=int, default=30)
     ap.add_argument("--variants", action="store_true",
                     help="also time the FP32-state and multinomial variants")
+    ap.add_argument("--tune", action="store_true", help="batch: run the autotuner first")
     return ap.parse_args()
+
+
+def source_digest(names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(CSRC, nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_profile_values(fname):
+    """`value key = v` lines of a committed counter summary (None if absent)."""
+    path = os.path.join(PROFILES, fname)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("value ") and "=" in line:
+                k, v = line[len("value "):].split("=", 1)
+                vals[k.strip()] = v.strip()
+    return vals
 
 
 def _bytes_per_particle(fp32: bool, gathered: bool) -> int:
@@ -53,6 +95,29 @@ def _bytes_per_particle(fp32: bool, gathered: bool) -> int:
     s = 4 if fp32 else 8
     return 2 * 4 * s + 2 * 8 + (4 if gathered else 0)
 
+
+def copy_gbs(nbytes=1 << 30, reps=5):
+    """Plain device-to-device copy: (read + write bytes) / time, best of reps."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = 0.0
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = max(best, 2 * nbytes / (a.elapsed_time(b) * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
+
+
+# ------------------------------------------------------------ particle filter
 
 def run_pf(args, n, fp32, scheme, steps, warmup, timing=True):
     import torch
@@ -63,7 +128,6 @@ def run_pf(args, n, fp32, scheme, steps, warmup, timing=True):
     T = max(args.T, T_needed)
     _, y = synth.pf_trajectory(T, synth.DATA_SEED[1])
     pf = ParticleFilter(n, y, seed=1, scheme=scheme, fp32_state=fp32)
-    stream = pf.stream
     pf.init()
     for t in range(1, 1 + warmup):
         pf.step(t)
@@ -89,7 +153,7 @@ def run_pf(args, n, fp32, scheme, steps, warmup, timing=True):
     hist = pf.history_host()
     flags = hist[:, L.SMC_H_FLAG]
     tot_bytes = 0.0
-    for k, t in enumerate(range(1 + warmup, 1 + warmup + steps)):
+    for t in range(1 + warmup, 1 + warmup + steps):
         tot_bytes += n * _bytes_per_particle(fp32, bool(flags[t - 1]))
     res = {
         "wall_s": wall,
@@ -106,7 +170,7 @@ def run_pf(args, n, fp32, scheme, steps, warmup, timing=True):
     return res
 
 
-def cpu_baseline(args):
+def cpu_baseline_pf(args):
     import oracle
     import synth
     n, T = args.cpu_sample_n, args.cpu_sample_T
@@ -116,25 +180,32 @@ def cpu_baseline(args):
     t0 = time.perf_counter()
     oracle.pf_run(cfg, y)
     wall = time.perf_counter() - t0
-    return {"value": n * T / wall, "unit": METRIC, "cores": 1, "kind": "oracle",
-            "sample": "tracking filter, N=%d, %d observations (init + %d steps), %s, "
-                      "single-threaded C oracle; wall %.2f s" % (n, T, T - 1, args.scheme, wall)}
+    return {"value": n * (T - 1) / wall, "unit": METRIC, "cores": 1, "kind": "oracle",
+            "sample": "tracking filter, N=%d, %d observations (init + %d timed steps; the "
+                      "init is inside the wall), %s, single-threaded C oracle; wall %.2f s"
+                      % (n, T, T - 1, args.scheme, wall)}
 
 
-def main():
-    args = _parse()
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); "
-              "multi-GPU sharding is described in DESIGN.md but not implemented" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
-    if not torch.cuda.is_available():
-        print("bench.py: no GPU visible", file=sys.stderr)
-        sys.exit(1)
+def pf_traffic():
+    """HBM bytes per move launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary, scaled by the copy-kernel calibration; None when the summary
+    was taken on another version of the kernel."""
+    v = read_profile_values("pf_move_c1_traffic.txt")
+    if not v or v.get("source_digest") != source_digest(PF_MOVE_SOURCES):
+        return None
+    fetch = float(v["fetch_kib_per_launch"]) * 1024 / float(v["copy_fetch_factor"])
+    write = float(v["write_kib_per_launch"]) * 1024 / float(v["copy_write_factor"])
+    return fetch + write
+
+
+def bench_pf(args):
     n = args.n
     main_res = run_pf(args, n, args.fp32_state, args.scheme, args.steps, args.warmup)
     achieved = main_res["move_bytes_avg"] / (main_res["move_ms_avg"] * 1e-3) / 1e9
+    traffic = None
+    if not args.fp32_state and n == 1 << 22 and args.scheme == "systematic":
+        traffic = pf_traffic()
+    T = max(args.T, 1 + args.warmup + args.steps)
     out = {
         "metric": METRIC,
         "value": main_res["value"],
@@ -150,17 +221,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": "tracking particle filter (constant-velocity model, Student-t "
                                "observations), N=%d, T=%d, %s, %s resampling at ESS<N/2, "
-                               "monitor every step" % (n, max(args.T, 1 + args.warmup + args.steps),
-                                                       "fp32 state" if args.fp32_state else "fp64",
-                                                       args.scheme),
-                   "n": n, "T": max(args.T, 1 + args.warmup + args.steps), "scheme": args.scheme},
+                               "monitor every step" % (n, T, "fp32 state" if args.fp32_state
+                                                       else "fp64", args.scheme),
+                   "n": n, "T": T, "scheme": args.scheme},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "pf_move_kernel (fused move + incremental log-weight)",
                      "avg_launch_ms": main_res["move_ms_avg"],
                      "bytes_per_launch": main_res["move_bytes_avg"]},
         "resample_fraction": main_res["resample_fraction"],
         "log_z": main_res["log_z"],
+        "hbm_copy_gbs": copy_gbs(),
     }
     if args.variants:
         var = {}
@@ -171,7 +242,143 @@ def main():
                          "move_gbs": r["move_bytes_avg"] / (r["move_ms_avg"] * 1e-3) / 1e9}
         out["variants"] = var
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args)
+        out["cpu_baseline"] = cpu_baseline_pf(args)
+    return out
+
+
+# ------------------------------------------------------------ mixture sampler
+
+def gmm_config(which, move):
+    import synth
+    if which == "gmm-c2":
+        K, n, nd, T = 4, 1 << 14, 1000, 100
+        y = synth.gmm_data_four_components(nd, synth.DATA_SEED[2])
+        move = move or "rw"
+    else:
+        K, n, nd, T = 6, 1 << 16, 10000, 200
+        y, _ = synth.gmm_data_spaced(nd, K, synth.DATA_SEED[3])
+        move = move or "mala"
+    return K, n, nd, T, y, move
+
+
+def bench_gmm(args):
+    import torch
+    import synth
+    from paper_1306_5583_amd import GmmSampler, _lib as L
+    K, n, nd, T, y, move = gmm_config(args.workload, args.move)
+    alphas = synth.prior_tempering(T, 4.0)
+    warm = GmmSampler(n, y, K, T, seed=1, move=move)
+    warm.run(alphas[:4])
+    torch.cuda.synchronize()
+    warm.close()
+    s = GmmSampler(n, y, K, T, seed=1, move=move)
+    blocks = 3 if K > 1 else 2
+    L.smc_profile_start(s.ctx, T * blocks)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    logz = s.run(alphas)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    blk_ms = L.smc_profile_read(s.ctx, T * blocks)
+    s.check()
+    hist = s.history_host()
+    terms_per_launch = n * nd * K
+    avg_ms = float(np.mean(blk_ms))
+    v = read_profile_values("gmm_block_%s_fp64.txt" % args.workload.split("-")[1])
+    flops = None
+    if v and v.get("source_digest") == source_digest(GMM_BLOCK_SOURCES) \
+            and v.get("move") == move:
+        flops = float(v["fp64_flops_per_term"]) * terms_per_launch
+    achieved = flops / (avg_ms * 1e-3) / 1e12 if flops else None
+    out = {
+        "metric": METRIC, "value": n * T / wall, "unit": METRIC, "n_gpus": 1, "steps": T,
+        "warmup": 3, "ms_per_step": 1e3 * wall / T, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "tempered Gaussian-mixture SMC sampler, K=%d, n=%d data, N=%d, "
+                               "T=%d, alpha=(t/T)^4, %s moves" % (K, nd, n, T, move),
+                   "K": K, "n_data": nd, "n": n, "T": T, "move": move},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS if achieved else None,
+                     "traffic": None, "kernel": "gmm_block_kernel (Metropolis block: proposal, "
+                     "mixture likelihood%s, accept)" % (" and gradient" if move == "mala" else ""),
+                     "avg_launch_ms": avg_ms, "terms_per_launch": terms_per_launch},
+        "terms_per_s": terms_per_launch / (avg_ms * 1e-3),
+        "log_z": logz,
+        "accept_rate": (hist[1:, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3].sum(axis=0) / (n * T)).tolist(),
+        "resamples": int(hist[1:, L.SMC_H_FLAG].sum()),
+    }
+    s.close()
+    return out
+
+
+# ------------------------------------------------------------ batched form
+
+def bench_batch(args):
+    import torch
+    import synth
+    import paper_1306_5583_amd as pkg
+    steps = 200
+    work = synth.batched_workload(steps)
+    specs = [pkg.PfSpec(**kw) if k == "pf" else pkg.GmmSpec(move="mala", **kw)
+             for k, kw in work]
+    br = pkg.BatchRunner(specs)
+    Ks = sorted({kw["K"] for k, kw in work if k == "gmm"})
+    if args.tune:
+        br.autotune(5, None)
+    waves = {K: br.waves(K) for K in Ks}
+    br.run(3, graph=True)          # warm-up (graph capture included)
+    br.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat = np.array(br.run(steps, graph=True, latencies=True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    br.check()
+    parts = sum(int(kw["n"]) for _, kw in work)
+    out = {
+        "metric": METRIC, "value": parts * steps / wall, "unit": METRIC, "n_gpus": 1,
+        "steps": steps, "warmup": 3, "ms_per_step": 1e3 * wall / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched: 128 tracking filters (N log-uniform in [2^10, 2^18]) "
+                               "+ 32 MALA mixture samplers (K in 2..8, n log-uniform in "
+                               "[500, 20000], N log-uniform in [2^12, 2^16]), 200 steps, one "
+                               "HIP graph per step", "problems": len(work),
+                   "particles": parts},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(lat.mean())},
+        "waves_per_tile": {str(k): v for k, v in waves.items()},
+        "tuned": bool(args.tune),
+    }
+    br.close()
+    return out
+
+
+def bench_copy(args):
+    nbytes = 1 << 30
+    return {"workload": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+            "gbs": copy_gbs(nbytes)}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus %d requested); "
+              "multi-GPU sharding is described in DESIGN.md but not implemented" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if args.workload == "pf":
+        out = bench_pf(args)
+    elif args.workload in ("gmm-c2", "gmm-c3"):
+        out = bench_gmm(args)
+    elif args.workload == "batch":
+        out = bench_batch(args)
+    else:
+        out = bench_copy(args)
     print(json.dumps(out), flush=True)
 
 

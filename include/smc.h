@@ -286,10 +286,11 @@ smc_status smc_draw_words(uint64_t seed, uint32_t step, uint32_t tag, uint32_t c
  * Restrictions: systematic resampling, double-precision tracking state,
  * the same move kind and sweep count for all mixture samplers.
  * ------------------------------------------------------------------------ */
-/* Timing of the sweep's dominant kernel (the tracking filter's move
- * kernel) by events carried in the kernel's own dispatch, so the stream
- * receives no extra packets: the next `count` move launches of this context
- * are timed (count = 0 disarms).  smc_profile_read waits for them and writes
+/* Timing of the sweep's dominant kernel by events carried in the kernel's
+ * own dispatch, so the stream receives no extra packets: the next `count`
+ * launches of the tracking filter's move kernel, or of the mixture
+ * sampler's Metropolis-block kernel (one per block), of this context are
+ * timed (count = 0 disarms).  smc_profile_read waits for them and writes
  * up to `capacity` durations in milliseconds, in launch order; *written
  * receives how many.  Host-side bookkeeping only; events are owned by the
  * context. */

@@ -649,12 +649,27 @@ hipError_t GmmK<K>::block(Ctx &c, int W, int32_t step, int block, int sweep, dou
     double *dst = gather_check ? (double *)c.other_ptr() : (double *)c.state_ptr();
     const Prob P = make_prob(c);
     (void)key;
-    if (c.cfg.move_kind == SMC_MOVE_MALA)
-        hipLaunchKernelGGL((gmm_block_kernel<K, true>), grid, blk, 0, c.stream, P, src, dst,
-                           (int)gather_check, W, (uint32_t)step, block, sweep, alpha, scale, step);
-    else
-        hipLaunchKernelGGL((gmm_block_kernel<K, false>), grid, blk, 0, c.stream, P, src, dst,
-                           (int)gather_check, W, (uint32_t)step, block, sweep, alpha, scale, step);
+    hipEvent_t e0, e1;
+    const bool timed = c.prof_take(&e0, &e1);
+    if (c.cfg.move_kind == SMC_MOVE_MALA) {
+        if (timed)
+            hipExtLaunchKernelGGL((gmm_block_kernel<K, true>), grid, blk, 0, c.stream, e0, e1, 0,
+                                  P, src, dst, (int)gather_check, W, (uint32_t)step, block, sweep,
+                                  alpha, scale, step);
+        else
+            hipLaunchKernelGGL((gmm_block_kernel<K, true>), grid, blk, 0, c.stream, P, src, dst,
+                               (int)gather_check, W, (uint32_t)step, block, sweep, alpha, scale,
+                               step);
+    } else {
+        if (timed)
+            hipExtLaunchKernelGGL((gmm_block_kernel<K, false>), grid, blk, 0, c.stream, e0, e1, 0,
+                                  P, src, dst, (int)gather_check, W, (uint32_t)step, block, sweep,
+                                  alpha, scale, step);
+        else
+            hipLaunchKernelGGL((gmm_block_kernel<K, false>), grid, blk, 0, c.stream, P, src, dst,
+                               (int)gather_check, W, (uint32_t)step, block, sweep, alpha, scale,
+                               step);
+    }
     return hipGetLastError();
 }
 
