@@ -18,7 +18,8 @@ oracle timed on a bounded sample of the same workload.
 Other workloads: --workload gmm-c2 / gmm-c3 (the tempered mixture sampler,
 FP64 vector-ALU bound), batch (many filters and samplers in one graph per
 step), copy (a plain device copy, the calibration kernel for the traffic
-counters and a measured HBM ceiling).
+counters and a measured HBM ceiling), study (GPU-seconds per log Z estimate
+within 0.05 nats, MALA against random-walk moves).
 """
 from __future__ import annotations
 
@@ -50,7 +51,7 @@ def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="pf",
-                    choices=["pf", "gmm-c2", "gmm-c3", "batch", "copy"])
+                    choices=["pf", "gmm-c2", "gmm-c3", "batch", "copy", "study"])
     ap.add_argument("--steps", type=int, default=189)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=1 << 22)
@@ -64,6 +65,17 @@ def _parse():
     ap.add_argument("--variants", action="store_true",
                     help="also time the FP32-state and multinomial variants")
     ap.add_argument("--tune", action="store_true", help="batch: run the autotuner first")
+    ap.add_argument("--study-problem", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--study-methods", default="mala,rw,rw:0.05")
+    ap.add_argument("--study-tol", type=float, default=0.05)
+    ap.add_argument("--study-seeds", type=int, default=16)
+    ap.add_argument("--study-ref-method", default=None)
+    ap.add_argument("--study-ref-log-z", type=float, default=None)
+    ap.add_argument("--study-ref-seeds", type=int, default=4)
+    ap.add_argument("--study-ref-n", type=int, default=1 << 18)
+    ap.add_argument("--study-ref-T", type=int, default=1600)
+    ap.add_argument("--study-T", default="50,100,200,400,800")
+    ap.add_argument("--study-logn", default="10,11,12,13,14,15,16")
     return ap.parse_args()
 
 
@@ -354,6 +366,102 @@ def bench_batch(args):
     return out
 
 
+# ------------------------------------------------- MALA vs random walk study
+
+def _method_scales(method, alphas):
+    """'mala' / 'mala:h' (MALA step h, default 0.05) or 'rw' / 'rw:b' (random
+    walk with the paper's per-block scales rescaled to base b, default 0.15):
+    the move kind and the per-step block scales."""
+    from paper_1306_5583_amd import mala_scales, rw_scales
+    kind, _, par = method.partition(":")
+    if kind == "mala":
+        h = float(par) if par else 0.05
+        return "mala", np.array([mala_scales(min(max(a, 0.0), 1.0), h) for a in alphas])
+    b = float(par) if par else 0.15
+    return "rw", np.array([rw_scales(min(max(a, 0.0), 1.0), b) for a in alphas])
+
+
+def _study_batch(y, K, n, T, method, seeds, seed0):
+    """`seeds` independent samplers of one configuration in one batch;
+    returns (log Z estimates, wall seconds of init + T graph replays)."""
+    import torch
+    import synth
+    import paper_1306_5583_amd as pkg
+    alphas = synth.prior_tempering(T, 4.0)
+    move, scales = _method_scales(method, alphas)
+    specs = [pkg.GmmSpec(n=n, y=y, K=K, alphas=alphas, scales=scales, move=move,
+                         seed=seed0 + s, problem_id=s) for s in range(seeds)]
+    br = pkg.BatchRunner(specs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    br.run(T, graph=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    br.check()
+    z = [br.log_z(i) for i in range(seeds)]
+    br.close()
+    return np.array(z), wall
+
+
+def bench_study(args):
+    """GPU-seconds per log Z estimate within 0.05 nats (root-mean-square over
+    seeds, against a high-effort reference run with the first method) for
+    MALA and random-walk moves.  Each configuration runs its seeds as one
+    batch; the cost of one estimate is the batch wall time over the seed
+    count."""
+    K, _, nd, _, y, _ = gmm_config("gmm-" + args.study_problem, None)
+    methods = args.study_methods.split(",")
+    ref_method = args.study_ref_method or methods[0]
+    if args.study_ref_log_z is not None:
+        zstar = args.study_ref_log_z
+        ref = {"log_z_given": zstar}
+    else:
+        zr, wall = _study_batch(y, K, args.study_ref_n, args.study_ref_T, ref_method,
+                                args.study_ref_seeds, 7000)
+        zstar = float(zr.mean())
+        ref = {"method": ref_method, "n": args.study_ref_n, "T": args.study_ref_T,
+               "log_z": zr.tolist(), "mean": zstar,
+               "se": float(zr.std(ddof=1) / np.sqrt(zr.size)), "wall_s": wall}
+        print("# reference %s N=%d T=%d: %s (%.1f s)" % (ref_method, args.study_ref_n,
+                                                       args.study_ref_T,
+                                                       np.round(zr, 4).tolist(), wall),
+              file=sys.stderr, flush=True)
+    Ts = [int(v) for v in args.study_T.split(",")]
+    Ns = [1 << int(v) for v in args.study_logn.split(",")]
+    grid = []
+    best = {}
+    for method in methods:
+        for T in Ts:
+            for n in Ns:
+                z, wall = _study_batch(y, K, n, T, method, args.study_seeds, 100000 + 1000 * T)
+                rmse = float(np.sqrt(np.mean((z - zstar) ** 2)))
+                cost = wall / args.study_seeds
+                grid.append({"method": method, "T": T, "n": n, "rmse": rmse,
+                             "bias": float(z.mean() - zstar), "sd": float(z.std(ddof=1)),
+                             "gpu_s": cost})
+                print("# %s T=%d N=%d rmse %.4f bias %+.4f sd %.4f gpu_s %.4f" % (
+                    method, T, n, rmse, z.mean() - zstar, z.std(ddof=1), cost),
+                    file=sys.stderr, flush=True)
+                if rmse <= args.study_tol and (method not in best
+                                               or cost < best[method]["gpu_s"]):
+                    best[method] = {"T": T, "n": n, "rmse": rmse, "gpu_s": cost}
+    rw_best = [b["gpu_s"] for m, b in best.items() if m.startswith("rw")]
+    mala_best = [b["gpu_s"] for m, b in best.items() if m.startswith("mala")]
+    out = {
+        "metric": "GMM-SMC GPU-s to +-%g nats log Z, MALA vs RW" % args.study_tol,
+        "workload": "tempered Gaussian-mixture sampler, %s data: K=%d, n=%d, alpha=(t/T)^4"
+                    % (args.study_problem, K, nd),
+        "reference": ref,
+        "tolerance_nats": args.study_tol,
+        "best": best,
+        "mala_over_best_rw_cost": (min(mala_best) / min(rw_best)
+                                   if mala_best and rw_best else None),
+        "seeds": args.study_seeds,
+        "grid": grid,
+    }
+    return out
+
+
 def bench_copy(args):
     nbytes = 1 << 30
     return {"workload": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
@@ -377,6 +485,8 @@ def main():
         out = bench_gmm(args)
     elif args.workload == "batch":
         out = bench_batch(args)
+    elif args.workload == "study":
+        out = bench_study(args)
     else:
         out = bench_copy(args)
     print(json.dumps(out), flush=True)
