@@ -124,27 +124,31 @@ struct MonDest {
     double *out;      // optional device output [rows]
 };
 
+// Sums the tile partials of every monitored row: wave w takes rows w,
+// w + NW, ...; lane l sums tiles l, l + 64, ... in order and the wave adds
+// its lanes (fixed order, so the result does not depend on timing).
 template <int NTHR>
 __device__ void mon_combine(const double *__restrict__ mon, int64_t ntiles, const MonDest &d,
                             double *__restrict__ hist, int64_t hist_len, double *red,
                             double *col)
 {
     constexpr int NW = NTHR / WAVE;
-    for (int r = 0; r <= d.rows; ++r) {
+    (void)red;
+    for (int r = wave_id(); r <= d.rows; r += NW) {
         const double *m = mon + (int64_t)r * ntiles;
         double a = 0.0;
-        int64_t b = threadIdx.x;
-        for (; b + 3 * NTHR < ntiles; b += 4 * NTHR) {
-            const double x0 = m[b], x1 = m[b + NTHR], x2 = m[b + 2 * NTHR], x3 = m[b + 3 * NTHR];
+        int64_t b = lane_id();
+        for (; b + 3 * WAVE < ntiles; b += 4 * WAVE) {
+            const double x0 = m[b], x1 = m[b + WAVE], x2 = m[b + 2 * WAVE], x3 = m[b + 3 * WAVE];
             a += x0;
             a += x1;
             a += x2;
             a += x3;
         }
-        for (; b < ntiles; b += NTHR)
+        for (; b < ntiles; b += WAVE)
             a += m[b];
-        a = block_sum<NW>(a, red);
-        if (threadIdx.x == 0)
+        a = wave_sum(a);
+        if (lane_id() == 0)
             col[r] = a;
     }
     __syncthreads();
@@ -964,13 +968,15 @@ hipError_t launch_resample_batch(const Prob *probs, const int2 *map, int64_t til
 // after a resample), column-major [1 + rows][ntiles], then one workgroup
 // combines the tiles in a fixed order.
 // ---------------------------------------------------------------------------
+constexpr int MON_GROUP = 8;
+
 template <typename T>
 __global__ __launch_bounds__(TPB) void mon_partial_kernel(
     const T *__restrict__ x, int rows, int64_t n, const double *__restrict__ lw,
     const int32_t *__restrict__ anc, const double *__restrict__ scalars, int gather_check,
     int reset_check, double *__restrict__ mon, int64_t ntiles)
 {
-    __shared__ double red[NWAVES];
+    __shared__ double red[NWAVES * MON_GROUP];
     const bool resampled = scalars[SMC_S_RESAMPLED] != 0.0;
     const bool gather = gather_check && resampled;
     const bool reset = reset_check && resampled;
@@ -988,19 +994,29 @@ __global__ __launch_bounds__(TPB) void mon_partial_kernel(
             w[k] = reset ? 1.0 : exp_nonpos_d(lw[i] - M);
         }
     }
-    double sw = w[0] + w[1] + w[2] + w[3];
-    sw = block_sum<NWAVES>(sw, red);
-    if (threadIdx.x == 0)
-        mon[blockIdx.x] = sw;
-    for (int r = 0; r < rows; ++r) {
-        double s = 0.0;
+    // column 0 = sum w, column 1 + r = sum w x_r; eight columns per barrier pair
+    for (int c0 = 0; c0 <= rows; c0 += MON_GROUP) {
+        double s[MON_GROUP];
 #pragma unroll
-        for (int k = 0; k < ITEMS; ++k)
-            if (w[k] != 0.0)
-                s += w[k] * (double)x[(int64_t)r * n + src[k]];
-        s = block_sum<NWAVES>(s, red);
-        if (threadIdx.x == 0)
-            mon[(int64_t)(1 + r) * ntiles + blockIdx.x] = s;
+        for (int g = 0; g < MON_GROUP; ++g) {
+            const int c = c0 + g;
+            s[g] = 0.0;
+            if (c == 0) {
+                s[g] = ((w[0] + w[1]) + w[2]) + w[3];
+            } else if (c <= rows) {
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k)
+                    if (w[k] != 0.0)
+                        s[g] += w[k] * (double)x[(int64_t)(c - 1) * n + src[k]];
+            }
+        }
+        block_sum_n<NWAVES, MON_GROUP>(s, red);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int g = 0; g < MON_GROUP; ++g)
+                if (c0 + g <= rows)
+                    mon[(int64_t)(c0 + g) * ntiles + blockIdx.x] = s[g];
+        }
     }
 }
 

@@ -303,6 +303,30 @@ __device__ __forceinline__ double block_max(double v, double *red)
     return s;
 }
 
+// Workgroup sums of R values at once: R independent wave reductions, then
+// one barrier pair; `red` holds NW * R doubles.  Every lane receives the sums.
+template <int NW, int R>
+__device__ __forceinline__ void block_sum_n(double (&v)[R], double *red)
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        v[r] = wave_sum(v[r]);
+    __syncthreads();
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            red[wave_id() * R + r] = v[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double a = red[r];
+        for (int w = 1; w < NW; ++w)
+            a += red[w * R + r];
+        v[r] = a;
+    }
+}
+
 // Inclusive prefix sum across one wave.
 __device__ __forceinline__ double wave_incl_scan(double v)
 {
@@ -391,12 +415,13 @@ __device__ __forceinline__ void tile_partial(const double (&lw)[ITEMS], TilePart
             s2 += e * e;
         }
     }
-    s1 = block_sum<NWAVES>(s1, red);
-    s2 = block_sum<NWAVES>(s2, red);
+    __shared__ double red2[2 * NWAVES];
+    double v[2] = {s1, s2};
+    block_sum_n<NWAVES, 2>(v, red2);
     if (threadIdx.x == 0) {
         out->m = m;
-        out->s1 = s1;
-        out->s2 = s2;
+        out->s1 = v[0];
+        out->s2 = v[1];
         out->pad = 0.0;
     }
 }

@@ -161,11 +161,12 @@ __device__ __forceinline__ void pf_move_tile(const Prob &P, const T *__restrict_
     if (FUSE)
         tile_partial(lwv, P.partials + tile, red);
     if (MON) {
+        __shared__ double red5[5 * NWAVES];
+        block_sum_n<NWAVES, 5>(ms, red5);
+        if (threadIdx.x == 0) {
 #pragma unroll
-        for (int r = 0; r < 5; ++r) {
-            const double v = block_sum<NWAVES>(ms[r], red);
-            if (threadIdx.x == 0)
-                P.mon[(int64_t)r * P.ntiles + tile] = v;
+            for (int r = 0; r < 5; ++r)
+                P.mon[(int64_t)r * P.ntiles + tile] = ms[r];
         }
     }
 }
