@@ -4,7 +4,7 @@
 //
 //  log_d(x):   x = 2^e m with m in [sqrt(1/2), sqrt(2)); with s = (m-1)/(m+1)
 //              log m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...)  (Abramowitz &
-//              Stegun 4.1.27), |s| <= 0.1716 so 12 terms reach 1e-19;
+//              Stegun 4.1.27), |s| <= 0.1716 so 11 terms reach 1e-18;
 //              log x = e ln2 + log m with ln2 split in a high and a low part.
 //  exp_d(x):   x = k ln2 + r with k = rint(x / ln2) and |r| <= ln2/2 (Cody &
 //              Waite reduction with ln2 in two parts), e^r by its Taylor series
@@ -16,7 +16,8 @@
 //              coefficients from gen_exp2_poly.py), scaled by 2^k.
 //  sincospi_d: sin(pi x), cos(pi x) by exact reduction to r = x - n/2,
 //              |r| <= 1/4, and the Taylor series of sin(pi r), cos(pi r)
-//              (truncation below 2e-22 for |pi r| <= pi/4), then the
+//              to r^17 / r^16 (truncation below 1e-17 for |pi r| <= pi/4),
+//              then the
 //              quadrant n mod 4.
 //
 // Accuracy (checked on the host against 50-digit references): a few ulp,
@@ -59,9 +60,41 @@ constexpr double kSinC[10] = {sin_c(0), sin_c(1), sin_c(2), sin_c(3), sin_c(4),
                               sin_c(5), sin_c(6), sin_c(7), sin_c(8), sin_c(9)};
 constexpr double kCosC[10] = {cos_c(0), cos_c(1), cos_c(2), cos_c(3), cos_c(4),
                               cos_c(5), cos_c(6), cos_c(7), cos_c(8), cos_c(9)};
+// a * b + c with c a wave-uniform constant held in a scalar register pair:
+// the fused multiply-add takes it as its scalar operand.  (Left to itself
+// the compiler moves each polynomial coefficient into vector registers
+// before a two-address multiply-add when the kernel is short of scalar
+// registers: two extra vector instructions per coefficient.)
+__host__ __device__ inline double fma_k(double a, double b, double c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+#else
+    return fma(a, b, c);
+#endif
+}
+
+// 1 / d for d in [1, 4]: the hardware estimate (exact on the host) refined by
+// two Newton steps.
+__host__ __device__ inline double recip_1_4(double d)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double q = __builtin_amdgcn_rcp(d);
+#else
+    double q = 1.0 / d;
+#endif
+    q = fma(q, fma(-d, q, 1.0), q);
+    q = fma(q, fma(-d, q, 1.0), q);
+    return q;
+}
 }  // namespace detail
 
-// Natural logarithm of a finite x > 0 (no special-case handling).
+// Natural logarithm of a finite x > 0 (no special-case handling).  The
+// atanh series needs 10 terms: the first omitted one is below 1e-18
+// relative for |s| <= 0.1716.
+constexpr int LOG_TERMS = 10;
 __host__ __device__ inline double log_pos_d(double x)
 {
     int e;
@@ -70,12 +103,16 @@ __host__ __device__ inline double log_pos_d(double x)
     m = lo ? m + m : m;
     e = lo ? e - 1 : e;
     const double f = m - 1.0;  // exact
-    const double s = f / (2.0 + f);
+    // s = f / (2 + f) from a refined reciprocal and one residual correction
+    const double d = 2.0 + f;
+    const double q = detail::recip_1_4(d);
+    double s = f * q;
+    s = fma(fma(-s, d, f), q, s);
     const double s2 = s * s;
-    double p = detail::kAtanhC[11];
+    double p = detail::kAtanhC[LOG_TERMS - 1];
 #pragma unroll
-    for (int k = 10; k >= 0; --k)
-        p = fma(p, s2, detail::kAtanhC[k]);
+    for (int k = LOG_TERMS - 2; k >= 0; --k)
+        p = detail::fma_k(p, s2, detail::kAtanhC[k]);
     // log m = 2s + 2s s^2 p, arranged around f for accuracy: 2s = f - s f
     const double hs = s * f;           // = f - 2s up to rounding
     const double lm = f - (hs - 2.0 * s * s2 * p);
@@ -105,7 +142,7 @@ __host__ __device__ inline double exp_nonpos_d(double x)
     double p = detail::kExpC[13];
 #pragma unroll
     for (int j = 12; j >= 0; --j)
-        p = fma(p, r, detail::kExpC[j]);
+        p = detail::fma_k(p, r, detail::kExpC[j]);
     return ldexp(p, (int)k);
 }
 
@@ -147,12 +184,13 @@ __host__ __device__ inline void sincospi_d(double x, double *sp, double *cp)
     const double n = rint(x + x);          // nearest multiple of 1/2
     const double r = fma(n, -0.5, x);      // exact, |r| <= 1/4
     const double r2 = r * r;
-    double s = detail::kSinC[9];
-    double c = detail::kCosC[9];
+    // nine terms each: the first omitted ones are below 1e-17 relative
+    double s = detail::kSinC[8];
+    double c = detail::kCosC[8];
 #pragma unroll
-    for (int k = 8; k >= 0; --k) {
-        s = fma(s, r2, detail::kSinC[k]);
-        c = fma(c, r2, detail::kCosC[k]);
+    for (int k = 7; k >= 0; --k) {
+        s = detail::fma_k(s, r2, detail::kSinC[k]);
+        c = detail::fma_k(c, r2, detail::kCosC[k]);
     }
     s *= r;
     const int q = (int)(long long)n & 3;
