@@ -734,10 +734,9 @@ __device__ __forceinline__ void resample_sys_tile(const Prob &P, int64_t b, uint
     __shared__ int wave_max[NWAVES];
     __shared__ int owner[RS_UCAP];
     __shared__ long long tile_lo;
+    __shared__ double sh_U;
     const int tid = threadIdx.x;
     const bool go = force != 0 || scalars[SMC_S_FLAG] != 0.0;
-    const uint4 wU = draw(P.key, 0, t, TAG_RESAMPLE, 0, P.problem_id);
-    const double U = u53(wU.x, wU.y);
     if (!go) {
         if (b == 0 && tid == 0)
             scalars[SMC_S_RESAMPLED] = 0.0;
@@ -757,7 +756,13 @@ __device__ __forceinline__ void resample_sys_tile(const Prob &P, int64_t b, uint
     const double Pb = prefix[b], Pb1 = prefix[b + 1];
     const double mb = P.partials[b].m;
     const double sc = mb > -INFINITY ? exp_nonpos_d(mb - M) : 0.0;
+    // the step's systematic offset: one lane draws it while the tile loads
+    if (tid == 0) {
+        const uint4 wU = draw(P.key, 0, t, TAG_RESAMPLE, 0, P.problem_id);
+        sh_U = u53(wU.x, wU.y);
+    }
     const TileCdf cdf = tile_cdf(lw, base, len, mb, sc, Pb, Pb1, red, wave_last, wave_pos);
+    const double U = sh_U;  // tile_cdf ends on a barrier
     const double nd = (double)n;
     const double r = nd / stot;
     // c(x) = min(N, max(0, ceil(x N / S - U))): the number of uniforms
