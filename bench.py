@@ -51,7 +51,7 @@ def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="pf",
-                    choices=["pf", "gmm-c2", "gmm-c3", "batch", "copy", "study"])
+                    choices=["pf", "pf-c0", "gmm-c2", "gmm-c3", "batch", "copy", "study"])
     ap.add_argument("--steps", type=int, default=189)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=1 << 22)
@@ -256,6 +256,47 @@ def bench_pf(args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_pf(args)
     return out
+
+
+def bench_pf_c0(args):
+    """The small filter (N = 1000, T = 100): launch-latency bound, so the
+    step is timed eagerly (three launches per step from the host) and as a
+    captured graph replay (the batched form with one problem)."""
+    import torch
+    import synth
+    import paper_1306_5583_amd as pkg
+    _, y = synth.pf_trajectory(100, synth.DATA_SEED[0])
+    steps = y.shape[0] - 1
+    pf = pkg.ParticleFilter(1000, y, seed=1)
+    pf.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        logz_eager = pf.run()
+    torch.cuda.synchronize()
+    eager_ms = 1e3 * (time.perf_counter() - t0) / (5 * steps)
+    pf.close()
+    br = pkg.BatchRunner([pkg.PfSpec(n=1000, y=y, seed=1)])
+    br.run(steps, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat = np.array(br.run(steps, graph=True, latencies=True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    logz_graph = br.log_z(0)
+    br.close()
+    return {
+        "metric": METRIC, "value": 1000 * steps / wall, "unit": METRIC, "n_gpus": 1,
+        "steps": steps, "warmup": 1, "ms_per_step": 1e3 * wall / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "tracking particle filter, N=1000, T=100, systematic at "
+                               "ESS<N/2, graph replay per step", "n": 1000, "T": 100},
+        "latency_ms": {"graph_p50": float(np.percentile(lat, 50)),
+                       "graph_p99": float(np.percentile(lat, 99)),
+                       "eager_mean": eager_ms},
+        "log_z": {"eager": logz_eager, "graph": logz_graph},
+    }
 
 
 # ------------------------------------------------------------ mixture sampler
@@ -481,6 +522,8 @@ def main():
         sys.exit(1)
     if args.workload == "pf":
         out = bench_pf(args)
+    elif args.workload == "pf-c0":
+        out = bench_pf_c0(args)
     elif args.workload in ("gmm-c2", "gmm-c3"):
         out = bench_gmm(args)
     elif args.workload == "batch":

@@ -275,17 +275,6 @@ smc_status smc_gmm_loglik_grad(const double *mu, const double *eta, const double
 smc_status smc_draw_words(uint64_t seed, uint32_t step, uint32_t tag, uint32_t call,
                           uint32_t problem, int64_t n, uint32_t *out, void *hip_stream);
 
-/* ------------------------------------------------------------------------
- * Batched form: many independent filters and samplers of different sizes
- * advanced together.  Each phase of a step (move / reweight, normalisation,
- * resampling, each Metropolis block) is ONE launch covering every problem's
- * tiles, the step index lives on the device, and a step can be captured
- * once into a HIP graph and replayed.  Every problem computes exactly what
- * its own single-problem context would (same kernels, same Philox counters
- * with its problem_id); the batch only changes how the work is launched.
- * Restrictions: systematic resampling, double-precision tracking state,
- * the same move kind and sweep count for all mixture samplers.
- * ------------------------------------------------------------------------ */
 /* Timing of the sweep's dominant kernel by events carried in the kernel's
  * own dispatch, so the stream receives no extra packets: the next `count`
  * launches of the tracking filter's move kernel, or of the mixture
@@ -297,40 +286,78 @@ smc_status smc_draw_words(uint64_t seed, uint32_t step, uint32_t tag, uint32_t c
 smc_status smc_profile_start(smc_ctx *ctx, int32_t count);
 smc_status smc_profile_read(smc_ctx *ctx, float *ms, int32_t capacity, int32_t *written);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent filters and samplers of different sizes
+ * advanced together.  Each phase of a step (move / reweight, normalisation,
+ * resampling, each Metropolis block) is ONE launch covering every problem's
+ * tiles, the step index lives on the device, and a step can be captured
+ * once into a HIP graph and replayed.  Every problem computes exactly what
+ * its own single-problem context would (same kernels, same Philox counters
+ * with its problem_id); the batch only changes how the work is launched.
+ * Restrictions: systematic resampling, double-precision tracking state,
+ * the same move kind and sweep count for all mixture samplers.
+ * ------------------------------------------------------------------------ */
 typedef struct smc_batch smc_batch;
 
 typedef struct smc_batch_problem {
-    smc_config cfg;          /* as for smc_create */
-    smc_buffers buf;         /* the problem's own device buffers (as for smc_create) */
-    const double *schedule;  /* GMM: device [schedule_len][4] = alpha_t and the mean,
-                                log-precision and logit block scales of step t; NULL for CV */
-    int32_t schedule_len;    /* GMM: rows of schedule (steps + 1) */
+    smc_config cfg;          /* as for smc_create (scheme must be systematic; a tracking
+                                filter must have precision SMC_F64) */
+    smc_buffers buf;         /* the problem's own device buffers, as for smc_create; the
+                                state of step t lives in state (t even) or state_alt
+                                (t odd) */
+    const double *schedule;  /* mixture samplers: device [schedule_len][4] = alpha_t and
+                                the mean, log-precision and logit block scales of step t
+                                (row 0: alpha_0 = 0); NULL for tracking filters */
+    int32_t schedule_len;    /* mixture samplers: rows of schedule (steps + 1) */
 } smc_batch_problem;
 
 /* Device bytes of the batch table (problem descriptors, tile maps, step
- * counter) the caller must provide to smc_batch_create. */
+ * counter) the caller must provide to smc_batch_create.  Validates every
+ * configuration (SMC_ERR_INVALID_ARG as smc_create would). */
 smc_status smc_batch_table_size(const smc_batch_problem *probs, int32_t nprob, size_t *bytes);
+/* Builds the batch over caller-owned memory: `table` (device, 256-byte
+ * aligned, at least smc_batch_table_size bytes) and every problem's buffers
+ * must outlive the batch; all work is enqueued on `hip_stream`, which must
+ * not be the legacy null stream when steps are captured.  Errors:
+ * SMC_ERR_INVALID_ARG (null or misaligned arguments, a configuration or
+ * buffer set smc_create would refuse, a mixture sampler without a
+ * schedule, a table that is too small), SMC_ERR_UNSUPPORTED (another
+ * resampling scheme, FP32 tracking state, mixture samplers with different
+ * move kinds or sweep counts), SMC_ERR_DEVICE (not a gfx950 device, or a
+ * copy failed).  Nothing is created on error. */
 smc_status smc_batch_create(const smc_batch_problem *probs, int32_t nprob, void *table,
                             size_t table_bytes, void *hip_stream, smc_batch **out);
+/* Releases the host object and its captured graph (not the caller's memory). */
 smc_status smc_batch_destroy(smc_batch *b);
 /* Picks the waves per 64-particle tile of every mixture-size group by timing
- * the likelihood kernel on the batch's own shapes (repeats launches per
- * candidate); reads / extends a text cache keyed by device, K and size
- * bucket when cache_path is non-NULL.  Leaves the state undefined: call
- * smc_batch_init afterwards. */
+ * the prior-draw + likelihood kernel on the batch's own shapes (`repeats`
+ * launches per candidate 1, 2, 4, 8, median kept); reads / extends a text
+ * cache of lines "<arch> K=<K> log2n=<l> log2nd=<m> W=<w>" when cache_path
+ * is non-NULL.  Synchronises the stream.  Leaves the state undefined and
+ * drops a captured graph: call smc_batch_init (and capture again)
+ * afterwards. */
 smc_status smc_batch_autotune(smc_batch *b, int32_t repeats, const char *cache_path);
+/* Waves per tile chosen for the mixture samplers with K components
+ * (SMC_ERR_INVALID_ARG when the batch has none). */
 smc_status smc_batch_waves(const smc_batch *b, int32_t K, int32_t *waves);
 /* Initialisation of every problem (as smc_init, then the t = 0
  * normalisation and resampling decision); device step counter = 0. */
 smc_status smc_batch_init(smc_batch *b);
-/* Enqueues one step of every problem (step index = device counter + 1). */
+/* Enqueues one step of every problem (step index = device counter + 1):
+ * tracking filters move + weight (completing the previous step's monitor),
+ * mixture samplers reweight; all normalise and resample if their ESS is low;
+ * mixture samplers then run their Metropolis blocks.  SMC_ERR_BAD_STATE
+ * before smc_batch_init or when a problem has no observation / schedule /
+ * history row left. */
 smc_status smc_batch_step(smc_batch *b);
-/* Captures one step into a HIP graph (replaces a previous capture). */
+/* Captures one step into a HIP graph (replaces a previous capture); the
+ * graph reads the step index from the device, so one capture serves every
+ * step. */
 smc_status smc_batch_capture(smc_batch *b);
-/* Launches the captured step. */
+/* Launches the captured step (same checks as smc_batch_step). */
 smc_status smc_batch_replay(smc_batch *b);
 /* Synchronises and checks every problem's device error word; *first_bad
- * receives the first failing problem or -1. */
+ * receives the first failing problem or -1 (SMC_ERR_NUMERIC if any). */
 smc_status smc_batch_check(smc_batch *b, int32_t *first_bad);
 const char *smc_batch_last_error(const smc_batch *b);
 
