@@ -278,3 +278,40 @@ def test_gradient_central_differences_c3_shape(lib, orc):
         fd = (loglik_and_grad(*plus, yd, False)[0] - loglik_and_grad(*minus, yd, False)[0]) / (2 * h)
         fd, gq = fd.cpu().numpy(), g[q].cpu().numpy()
         assert np.all(np.abs(fd - gq) <= 1e-6 * np.abs(gq) + 1e-4), (p, r)
+
+
+def test_lockstep_c2_full_size(lib, orc):
+    # the C2 shape (N = 2^14, K = 4, n = 1000): two steps in lock-step
+    _lockstep_gmm(lib, orc, 1 << 14, 4, 1000, 2, "rw", power=1.0)
+
+
+def test_c3_shape_sampled_particles(lib, orc):
+    """The C3 shape (N = 2^16, K = 6, n = 10^4, MALA), three steps: the cached
+    log-likelihood, log prior and gradient rows of sampled particles against
+    the oracle one by one, weights and acceptance counts by their
+    invariants."""
+    pkg, L = lib
+    K, n, nd, T = 6, 1 << 16, 10000, 3
+    y, _ = synth.gmm_data_spaced(nd, K, synth.DATA_SEED[3])
+    alphas = synth.prior_tempering(200, 4.0)[:T + 1] * 1e3   # larger steps, same shape
+    alphas = np.minimum(alphas, 1.0)
+    s = pkg.GmmSampler(n, y, K, T, seed=4, move="mala")
+    s.run(alphas)
+    s.check()
+    D = 3 * K - 1
+    st = s.state().cpu().numpy()
+    ocfg = orc.gmm_cfg(n, 4, K, move="mala")
+    rng = np.random.default_rng(2)
+    for i in rng.integers(0, n, 12):
+        phi = st[:D, i]
+        v, g = orc.gmm_loglik(phi, K, y, grad=True)
+        assert abs(st[D, i] - v) <= 1e-12 * (abs(v) + nd), i
+        lp = orc.gmm_logprior(ocfg, phi)
+        assert abs(st[D + 1, i] - lp) <= 1e-12 * (abs(lp) + 10), i
+        assert_close_l1(st[D + 2:D + 2 + D, i], g, np.abs(g) + 2 * nd, 1e-12, "grad %d" % i)
+    h = s.history_host()
+    assert np.all(np.isfinite(h[:T + 1, L.SMC_H_LOGZ]))
+    ess = h[1:T + 1, L.SMC_H_ESS]
+    assert np.all(ess >= 1.0) and np.all(ess <= n * (1 + 1e-12))
+    acc = h[1:T + 1, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3]
+    assert np.all(acc >= 0) and np.all(acc <= n) and np.all(acc == np.round(acc))
