@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <new>
+#include <algorithm>
 #include <string>
 
 #include "smc_internal.hpp"
@@ -36,7 +37,16 @@ Workspace plan_workspace(const smc_config &cfg)
     w.prefix = off;
     off = align256(off + sizeof(double) * (size_t)(ntiles + 1));
     w.mon = off;
-    off = align256(off + sizeof(double) * MON_STRIDE * (size_t)ntiles);
+    {
+        // columns: sum w and the monitored rows (the tracking state, or the
+        // mixture parameters and log-likelihood)
+        const int64_t cols = cfg.model == SMC_MODEL_CV_TRACK ? 5 : 3 * (int64_t)cfg.K + 1;
+        const int64_t t64 = ceil_div(n, WAVE);
+        int64_t words = (int64_t)MON_STRIDE * ntiles;
+        if (t64 <= MON64_MAX_TILES)
+            words = std::max<int64_t>(words, cols * t64);
+        off = align256(off + sizeof(double) * (size_t)words);
+    }
     w.counters = off;
     off = align256(off + sizeof(int32_t) * 16);
     if (cfg.scheme == SMC_RS_MULTINOMIAL) {

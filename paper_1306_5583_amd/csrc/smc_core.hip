@@ -1025,6 +1025,50 @@ __global__ __launch_bounds__(TPB) void mon_partial_kernel(
     }
 }
 
+// The same partials per 64-particle tile: one wave per workgroup, one
+// particle per lane, no barriers.  Many more workgroups for the same work,
+// which is what a population too small to fill the chip with 1024-particle
+// tiles needs.
+template <typename T>
+__global__ __launch_bounds__(WAVE) void mon_partial64_kernel(
+    const T *__restrict__ x, int rows, int64_t n, const double *__restrict__ lw,
+    const int32_t *__restrict__ anc, const double *__restrict__ scalars, int gather_check,
+    int reset_check, double *__restrict__ mon, int64_t ntiles)
+{
+    const bool resampled = scalars[SMC_S_RESAMPLED] != 0.0;
+    const bool gather = gather_check && resampled;
+    const bool reset = reset_check && resampled;
+    const double M = scalars[SMC_S_M];
+    const int64_t i = (int64_t)blockIdx.x * WAVE + lane_id();
+    double w = 0.0;
+    int64_t src = 0;
+    if (i < n) {
+        src = gather ? (int64_t)anc[i] : i;
+        w = reset ? 1.0 : exp_nonpos_d(lw[i] - M);
+    }
+    for (int c0 = 0; c0 <= rows; c0 += MON_GROUP) {
+        double v[MON_GROUP];
+#pragma unroll
+        for (int g = 0; g < MON_GROUP; ++g) {
+            const int c = c0 + g;
+            v[g] = 0.0;
+            if (c == 0)
+                v[g] = w;
+            else if (c <= rows && w != 0.0)
+                v[g] = w * (double)x[(int64_t)(c - 1) * n + src];
+        }
+#pragma unroll
+        for (int g = 0; g < MON_GROUP; ++g)
+            v[g] = wave_sum(v[g]);
+        if (lane_id() == 0) {
+#pragma unroll
+            for (int g = 0; g < MON_GROUP; ++g)
+                if (c0 + g <= rows)
+                    mon[(int64_t)(c0 + g) * ntiles + blockIdx.x] = v[g];
+        }
+    }
+}
+
 __global__ __launch_bounds__(FIN_TPB) void mon_final_kernel(const double *__restrict__ mon,
                                                             int64_t ntiles, MonDest md,
                                                             double *__restrict__ hist,
@@ -1038,20 +1082,30 @@ __global__ __launch_bounds__(FIN_TPB) void mon_final_kernel(const double *__rest
 hipError_t launch_monitor(Ctx &c, int32_t step, double *out_dev, int rows, bool gather_pending,
                           bool reset_pending)
 {
-    const dim3 grid((unsigned)c.ntiles);
-    if (c.elem_bytes == 4)
+    // 64-particle tiles up to MON64_MAX_TILES of them, 1024-particle tiles beyond
+    const int64_t t64 = ceil_div(c.n, WAVE);
+    const bool small = t64 <= MON64_MAX_TILES;
+    const int64_t ntm = small ? t64 : c.ntiles;
+    const dim3 grid((unsigned)ntm);
+#define SMC_MON_ARGS(T)                                                                          \
+    (const T *)c.state_ptr(), rows, c.n, c.buf.log_weight, c.buf.ancestors, c.buf.scalars,       \
+        (int)gather_pending, (int)reset_pending, c.mon(), ntm
+    if (small && c.elem_bytes == 4)
+        hipLaunchKernelGGL(mon_partial64_kernel<float>, grid, dim3(WAVE), 0, c.stream,
+                           SMC_MON_ARGS(float));
+    else if (small)
+        hipLaunchKernelGGL(mon_partial64_kernel<double>, grid, dim3(WAVE), 0, c.stream,
+                           SMC_MON_ARGS(double));
+    else if (c.elem_bytes == 4)
         hipLaunchKernelGGL(mon_partial_kernel<float>, grid, dim3(TPB), 0, c.stream,
-                           (const float *)c.state_ptr(), rows, c.n, c.buf.log_weight,
-                           c.buf.ancestors, c.buf.scalars, (int)gather_pending,
-                           (int)reset_pending, c.mon(), c.ntiles);
+                           SMC_MON_ARGS(float));
     else
         hipLaunchKernelGGL(mon_partial_kernel<double>, grid, dim3(TPB), 0, c.stream,
-                           (const double *)c.state_ptr(), rows, c.n, c.buf.log_weight,
-                           c.buf.ancestors, c.buf.scalars, (int)gather_pending,
-                           (int)reset_pending, c.mon(), c.ntiles);
+                           SMC_MON_ARGS(double));
+#undef SMC_MON_ARGS
     const MonDest md = mon_dest(c, step, rows, out_dev);
-    hipLaunchKernelGGL(mon_final_kernel, dim3(1), dim3(FIN_TPB), 0, c.stream, c.mon(),
-                       c.ntiles, md, c.buf.history, c.buf.history_len);
+    hipLaunchKernelGGL(mon_final_kernel, dim3(1), dim3(FIN_TPB), 0, c.stream, c.mon(), ntm, md,
+                       c.buf.history, c.buf.history_len);
     return hipGetLastError();
 }
 

@@ -19,7 +19,8 @@ namespace smc {
 struct Workspace {
     size_t partials;   // TilePartial[ntiles]
     size_t prefix;     // double[ntiles + 1]: cumulative-weight tile offsets
-    size_t mon;        // double[ntiles * MON_STRIDE]: monitor partial sums
+    size_t mon;        // monitor partial sums: double[MON_STRIDE * ntiles], or per
+                       // 64-particle tile double[columns * n/64] when that is larger
     size_t g;          // double[n + 1]: multinomial cumulative exponentials
     size_t gtile;      // double[gtiles]: tile sums of the exponentials
     size_t gprefix;    // double[gtiles + 1]
@@ -27,7 +28,12 @@ struct Workspace {
     size_t total;
 };
 
-constexpr int MON_STRIDE = 32;  // monitor partial: sum w, then up to 31 weighted rows
+// Monitor partial columns per tile: sum w, then up to 63 weighted rows (the
+// mixture's 3K - 1 parameters and its log-likelihood for K <= 16: 49).
+constexpr int MON_STRIDE = 64;
+// The standalone monitor uses 64-particle tiles while there are at most this
+// many of them (populations up to 2^20), 1024-particle tiles beyond.
+constexpr int64_t MON64_MAX_TILES = 16384;
 
 // Observation log-density of the tracking model for both coordinates:
 // Student-t with nu degrees of freedom and scale s per coordinate,

@@ -315,3 +315,27 @@ def test_c3_shape_sampled_particles(lib, orc):
     assert np.all(ess >= 1.0) and np.all(ess <= n * (1 + 1e-12))
     acc = h[1:T + 1, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3]
     assert np.all(acc >= 0) and np.all(acc <= n) and np.all(acc == np.round(acc))
+
+
+@pytest.mark.parametrize("K", [3, 12, 16])
+def test_monitor_all_rows_against_oracle(lib, orc, K):
+    # importance-sampling estimates of every parameter row and the
+    # log-likelihood (up to 3K = 48 rows for K = 16) after each step
+    pkg, L = lib
+    n, nd, T = 3000, 60, 3
+    y, _ = synth.gmm_data_spaced(nd, K, 17)
+    s = pkg.GmmSampler(n, y, K, T, seed=6)
+    alphas = synth.prior_tempering(T, 1.0)
+    s.init()
+    D = 3 * K - 1
+    for t in range(1, T + 1):
+        s.step(t, float(alphas[t]))
+        torch.cuda.synchronize()
+        est = s.monitor_out.cpu().numpy()
+        x = s.state().cpu().numpy()[:D + 1]
+        lw = s.log_weight.cpu().numpy()
+        if s.scalars_host()[L.SMC_S_RESAMPLED] != 0.0:
+            lw = np.zeros(n)          # weights restart after a resample
+        ref = orc.weighted_mean(x, lw)
+        assert_close_l1(est, ref, np.abs(x).mean(axis=1) + 1.0, 1e-11, "monitor K=%d t=%d" % (K, t))
+    s.check()
