@@ -47,7 +47,8 @@ def _mass(ll, alpha=1.0):
     return np.abs(ll) * max(alpha, 1.0) + 50.0
 
 
-@pytest.mark.parametrize("K,move", [(1, "rw"), (4, "rw"), (3, "mala"), (6, "mala")])
+@pytest.mark.parametrize("K,move", [(1, "rw"), (4, "rw"), (3, "mala"), (6, "mala"),
+                                    (10, "mala"), (13, "rw"), (16, "mala")])
 def test_init_parity(lib, orc, K, move):
     pkg, L = lib
     n, nd = 3001, 257
@@ -164,6 +165,13 @@ def test_lockstep(lib, orc, n, K, nd, move):
     _lockstep_gmm(lib, orc, n, K, nd, 12, move)
 
 
+@pytest.mark.parametrize("n,K,nd,move", [(1100, 9, 70, "mala"), (1500, 12, 50, "rw"),
+                                         (1030, 16, 40, "mala")])
+def test_lockstep_large_k(lib, orc, n, K, nd, move):
+    # the K >= 9 kernels keep part of their state in scratch memory
+    _lockstep_gmm(lib, orc, n, K, nd, 4, move)
+
+
 def test_lockstep_two_sweeps(lib, orc):
     _lockstep_gmm(lib, orc, 2500, 4, 120, 6, "rw", sweeps=2)
 
@@ -206,7 +214,7 @@ def test_alpha_zero_prior_invariance(lib):
     assert np.all(np.abs(w.mean(axis=1) - 0.25) < 5 * math.sqrt(0.0375 / n))
 
 
-@pytest.mark.parametrize("K", [1, 2, 6, 8])
+@pytest.mark.parametrize("K", [1, 2, 6, 8, 11, 16])
 def test_loglik_grad_entry(lib, orc, K):
     pkg, L = lib
     n, nd = 64, 10000
