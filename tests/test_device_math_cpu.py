@@ -27,5 +27,5 @@ def test_math_functions_within_few_ulp(tmp_path):
     assert vals["special"] == "1"
     assert float(vals["exp_ulp"]) < 4.0
     assert vals["exp_special"] == "1"
-    assert float(vals["exp2_ulp"]) < 2.0
+    assert float(vals["exp2_ulp"]) < 4.0
     assert vals["exp2_special"] == "1"
