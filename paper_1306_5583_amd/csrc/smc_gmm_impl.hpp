@@ -187,17 +187,26 @@ struct MixLik {
         }
     }
 
-    // accumulate a contiguous chunk of the data with wave-uniform loads
+    // accumulate a contiguous chunk of the data with wave-uniform loads; in
+    // the two-point loop the next pair is loaded one iteration ahead
     __device__ __forceinline__ void chunk(const double *__restrict__ y, int64_t k0, int64_t k1)
     {
         int64_t k = k0;
         while (k < k1) {
             const int64_t kend = min(k + FLUSH, k1);
             if (K <= 8) {  // two points per iteration while registers allow
-                for (; k + 2 <= kend; k += 2) {
-                    const double y0 = y[k], y1 = y[k + 1];
+                if (k + 2 <= kend) {
+                    double y0 = y[k], y1 = y[k + 1];
+                    for (; k + 4 <= kend; k += 2) {
+                        const double n0 = y[k + 2], n1 = y[k + 3];
+                        point(y0);
+                        point(y1);
+                        y0 = n0;
+                        y1 = n1;
+                    }
                     point(y0);
                     point(y1);
+                    k += 2;
                 }
             }
             for (; k < kend; ++k)
@@ -427,6 +436,19 @@ struct Proposal {
     }
 };
 
+// Values of the epilogue that do not depend on the likelihood, computed
+// before the data loop by the last wave and kept in LDS (one column per
+// lane) until wave 0 takes the decision: the proposal's log prior, the log of
+// the accept uniform, the proposed block coordinates and, for MALA, the
+// forward proposal term, the prior gradient at the proposal (block
+// coordinates) and the proposed mixture weights omega'_j (the z-gradient
+// subtracts n omega'_j).
+template <int K, bool MALA>
+struct BlockStash {
+    static constexpr int LPP = 0, LOGU = 1, FWD = 2, PROP = 3, GP = 3 + K, ZC = 3 + 2 * K;
+    static constexpr int ROWS = MALA ? 3 + 3 * K - 1 : 3 + K;
+};
+
 template <int K, bool MALA>
 __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__restrict__ src,
                                                double *__restrict__ dst, int full, int W,
@@ -434,7 +456,9 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
                                                double alpha, double scale, int32_t step)
 {
     constexpr int D = 3 * K - 1;
+    using S = BlockStash<K, MALA>;
     __shared__ double red[GMM_RED_GROUP * GMM_MAXW * WAVE];
+    __shared__ double stash[S::ROWS * WAVE];
     const int32_t *__restrict__ anc = P.anc;
     const int64_t n = P.n, nd = P.n_data;
     const double *__restrict__ y = P.data;
@@ -444,12 +468,14 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
     double *__restrict__ hist = P.hist;
     const int64_t hist_len = P.hist_len;
     const bool gather = full && P.scalars[SMC_S_RESAMPLED] != 0.0;
-    const int64_t i = tile * WAVE + lane_id();
+    const int lane = lane_id();
+    const int64_t i = tile * WAVE + lane;
     const bool valid = i < n;
     const int64_t si = valid ? (gather ? (int64_t)anc[i] : i) : 0;
     const uint32_t ii = (uint32_t)(valid ? i : 0);
     const int off = block * K;
     const int dim = block == 2 ? K - 1 : K;
+    const double h2 = scale * scale;
     MixLik<K, MALA> L;
     {
         Proposal<K, MALA> Q;
@@ -457,53 +483,78 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
         double logw[K];
         log_weights<K>(Q.prop, logw);
         L.setup(Q.prop, logw);
+        if (__builtin_amdgcn_readfirstlane(wave_id()) == W - 1) {
+            stash[S::LPP * WAVE + lane] = log_prior<K>(Q.prop, logw, pr);
+            const uint4 wa = draw(key, ii, t, TAG_MH_ACCEPT, (uint32_t)(4 * sweep + block), p);
+            stash[S::LOGU * WAVE + lane] = log_d(u53(wa.x, wa.y));
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                const int mm = q - off;
+                if (mm >= 0 && mm < dim) {
+                    stash[(S::PROP + mm) * WAVE + lane] = Q.prop[q];
+                    if (MALA)
+                        stash[(S::GP + mm) * WAVE + lane] = log_prior_grad<K>(Q.prop, logw, pr, q);
+                }
+            }
+            if (MALA) {
+                stash[S::FWD * WAVE + lane] = Q.fwd;
+#pragma unroll
+                for (int j = 0; j < K - 1; ++j)
+                    stash[(S::ZC + j) * WAVE + lane] = exp_d(logw[j]);
+            }
+        }
     }
     int64_t k0, k1;
     data_chunk(nd, W, &k0, &k1);
     L.chunk(y, k0, k1);
+    double ll0 = 0.0, lp0 = 0.0;
+    if (wave_id() == 0) {
+        ll0 = src[(int64_t)D * n + si];
+        lp0 = src[(int64_t)(D + 1) * n + si];
+    }
     combine_waves<K, MALA>(L, W, red);
     if (wave_id() != 0)
         return;
-    Proposal<K, MALA> Q;
-    Q.build(src, n, si, ii, key, t, p, block, sweep, alpha, scale, pr);
-    double logw[K];
-    log_weights<K>(Q.prop, logw);
-    const double ll0 = src[(int64_t)D * n + si];
-    const double lp0 = src[(int64_t)(D + 1) * n + si];
-    const double lpp = log_prior<K>(Q.prop, logw, pr);
+    double phi[D > 0 ? D : 1];
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+        phi[q] = src[(int64_t)q * n + si];
+    const double lpp = stash[S::LPP * WAVE + lane];
     const double cur = alpha == 0.0 ? lp0 : lp0 + alpha * ll0;
     double logr = (alpha == 0.0 ? lpp : lpp + alpha * L.ll) - cur;
     double gnew[MALA ? D : 1];
     if (MALA) {
-        const double h2 = scale * scale;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             gnew[j] = L.gmu[j];
             gnew[K + j] = L.geta[j];
             if (j < K - 1)
-                gnew[2 * K + j] = z_grad<K>(L.gr[j], logw[j], nd);
+                gnew[2 * K + j] = L.gr[j] - (double)nd * stash[(S::ZC + j) * WAVE + lane];
         }
         double bwd = 0.0;
 #pragma unroll
         for (int q = 0; q < D; ++q) {
             const int mm = q - off;
             if (mm >= 0 && mm < dim) {
-                double g2 = log_prior_grad<K>(Q.prop, logw, pr, q);
+                double g2 = stash[(S::GP + mm) * WAVE + lane];
                 if (alpha != 0.0)
                     g2 += alpha * gnew[q];
-                const double b = Q.phi[q] - Q.prop[q] - 0.5 * h2 * g2;
+                const double b = phi[q] - stash[(S::PROP + mm) * WAVE + lane] - 0.5 * h2 * g2;
                 bwd += b * b;
             }
         }
-        logr += (Q.fwd - bwd) / (2.0 * h2);
+        logr += (stash[S::FWD * WAVE + lane] - bwd) / (2.0 * h2);
     }
-    const uint4 wa = draw(key, ii, t, TAG_MH_ACCEPT, (uint32_t)(4 * sweep + block), p);
-    const bool acc = valid && log_d(u53(wa.x, wa.y)) <= logr;
+    const bool acc = valid && stash[S::LOGU * WAVE + lane] <= logr;
     if (valid) {
         if (full) {
 #pragma unroll
-            for (int q = 0; q < D; ++q)
-                dst[(int64_t)q * n + i] = acc ? Q.prop[q] : Q.phi[q];
+            for (int q = 0; q < D; ++q) {
+                const int mm = q - off;
+                const bool inb = mm >= 0 && mm < dim;
+                dst[(int64_t)q * n + i] =
+                    (acc && inb) ? stash[(S::PROP + (inb ? mm : 0)) * WAVE + lane] : phi[q];
+            }
             dst[(int64_t)D * n + i] = acc ? L.ll : ll0;
             dst[(int64_t)(D + 1) * n + i] = acc ? lpp : lp0;
             if (MALA) {
@@ -514,9 +565,11 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
             }
         } else if (acc) {
 #pragma unroll
-            for (int q = 0; q < D; ++q)
-                if (q >= off && q < off + dim)
-                    dst[(int64_t)q * n + i] = Q.prop[q];
+            for (int q = 0; q < D; ++q) {
+                const int mm = q - off;
+                if (mm >= 0 && mm < dim)
+                    dst[(int64_t)q * n + i] = stash[(S::PROP + mm) * WAVE + lane];
+            }
             dst[(int64_t)D * n + i] = L.ll;
             dst[(int64_t)(D + 1) * n + i] = lpp;
             if (MALA) {
@@ -528,7 +581,7 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
     }
     // count accepted proposals of this wave
     const unsigned long long bal = __ballot(acc);
-    if (lane_id() == 0 && hist && step >= 0 && step < hist_len && bal)
+    if (lane == 0 && hist && step >= 0 && step < hist_len && bal)
         atomicAdd(&hist[(int64_t)step * SMC_HIST_COLS + SMC_H_ACC0 + block],
                   (double)__popcll(bal));
 }
