@@ -124,32 +124,53 @@ struct MonDest {
     double *out;      // optional device output [rows]
 };
 
-// Sums the tile partials of every monitored row: wave w takes rows w,
-// w + NW, ...; lane l sums tiles l, l + 64, ... in order and the wave adds
-// its lanes (fixed order, so the result does not depend on timing).
+// Sums the tile partials of every monitored row with the whole workgroup:
+// thread t adds tiles t, t + NTHR, t + 2 NTHR, ... in order (MON_IT of them
+// loaded at once, two rows at a time), each wave adds its lanes, and thread r
+// adds the NW wave sums of row r in wave order, so the result does not depend
+// on timing.  `red` holds MON_STRIDE * NW doubles, `col` MON_STRIDE.
+constexpr int MON_IT = 8;
 template <int NTHR>
 __device__ void mon_combine(const double *__restrict__ mon, int64_t ntiles, const MonDest &d,
                             double *__restrict__ hist, int64_t hist_len, double *red,
                             double *col)
 {
     constexpr int NW = NTHR / WAVE;
-    (void)red;
-    for (int r = wave_id(); r <= d.rows; r += NW) {
-        const double *m = mon + (int64_t)r * ntiles;
-        double a = 0.0;
-        int64_t b = lane_id();
-        for (; b + 3 * WAVE < ntiles; b += 4 * WAVE) {
-            const double x0 = m[b], x1 = m[b + WAVE], x2 = m[b + 2 * WAVE], x3 = m[b + 3 * WAVE];
-            a += x0;
-            a += x1;
-            a += x2;
-            a += x3;
+    const int tid = threadIdx.x, w = wave_id();
+    for (int r0 = 0; r0 <= d.rows; r0 += 2) {
+        const bool two = r0 + 1 <= d.rows;
+        const double *m0 = mon + (int64_t)r0 * ntiles;
+        const double *m1 = two ? m0 + ntiles : m0;
+        double a0 = 0.0, a1 = 0.0;
+        for (int64_t base = 0; base < ntiles; base += (int64_t)MON_IT * NTHR) {
+            double x0[MON_IT], x1[MON_IT];
+#pragma unroll
+            for (int k = 0; k < MON_IT; ++k) {
+                const int64_t b = base + (int64_t)k * NTHR + tid;
+                x0[k] = b < ntiles ? m0[b] : 0.0;
+                x1[k] = b < ntiles ? m1[b] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < MON_IT; ++k) {
+                a0 += x0[k];
+                a1 += x1[k];
+            }
         }
-        for (; b < ntiles; b += WAVE)
-            a += m[b];
-        a = wave_sum(a);
-        if (lane_id() == 0)
-            col[r] = a;
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        if (lane_id() == 0) {
+            red[r0 * NW + w] = a0;
+            if (two)
+                red[(r0 + 1) * NW + w] = a1;
+        }
+    }
+    __syncthreads();
+    if (tid <= d.rows) {
+        double a = 0.0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v)
+            a += red[tid * NW + v];
+        col[tid] = a;
     }
     __syncthreads();
     if ((int)threadIdx.x < d.rows) {
@@ -165,36 +186,53 @@ __device__ void mon_combine(const double *__restrict__ mon, int64_t ntiles, cons
 
 constexpr int FIN_MON_ROWS = 4;  // rows a move can carry (the tracking state)
 
-// Single pass over at most FIN_PASS tile partials: lane t owns FIN_IT
-// consecutive tiles.  The cumulative offsets are the lane's running sums on
-// top of the workgroup scan of the lane totals, each clamped to the lane's
-// inclusive value, which is exactly the next lane's starting offset (and the
-// next wave's: the wave totals are summed in order), so the offsets never
-// decrease.  The sum of squares rides on the same barrier pair.
+// Single pass over at most FIN_PASS tile partials.  The partials are read
+// coalesced (lane t of the workgroup takes tiles t, t + FIN_TPB, ...), the
+// scaled tile weights s1 exp(m - M) go through LDS, and lane t then owns the
+// FIN_IT consecutive tiles from FIN_IT t.  (Reading each lane's consecutive
+// 256 bytes directly touches every cache line from FIN_IT lanes' loads and
+// thrashes the vector L1 once the partials outgrow it.)  The cumulative
+// offsets are the lane's running sums on top of the workgroup scan of the
+// lane totals, each clamped to the lane's inclusive value, which is exactly
+// the next lane's starting offset (and the next wave's: the wave totals are
+// summed in order), so the offsets never decrease; they return through LDS
+// for coalesced stores.  The sum of squares rides on the same barrier pair.
+// LDS slot of tile b: one pad double after every FIN_IT (two-way bank
+// conflicts at most on both the strided writes and the consecutive reads).
+__device__ __forceinline__ int fin_slot(int b) { return b + b / FIN_IT; }
+constexpr int FIN_LDS = FIN_PASS + FIN_PASS / FIN_IT;
+
 __device__ __forceinline__ void normalise_one_pass(const TilePartial *__restrict__ part,
                                                    int64_t ntiles, double *__restrict__ prefix,
-                                                   double *red, double *M_out, double *S1_out,
-                                                   double *S2_out)
+                                                   double *red, double *wl, double *M_out,
+                                                   double *S1_out, double *S2_out)
 {
     const int tid = threadIdx.x;
-    const int64_t b0 = (int64_t)tid * FIN_IT;
     TilePartial q[FIN_IT];
 #pragma unroll
-    for (int k = 0; k < FIN_IT; ++k)
-        q[k] = b0 + k < ntiles ? part[b0 + k] : TilePartial{-INFINITY, 0.0, 0.0, 0.0};
+    for (int k = 0; k < FIN_IT; ++k) {
+        const int64_t b = (int64_t)k * FIN_TPB + tid;
+        q[k] = b < ntiles ? part[b] : TilePartial{-INFINITY, 0.0, 0.0, 0.0};
+    }
     double m = -INFINITY;
 #pragma unroll
     for (int k = 0; k < FIN_IT; ++k)
         m = fmax(m, q[k].m);
     const double M = block_max<FIN_NW>(m, red);
-    double e[FIN_IT];
-    double run = 0.0, s2 = 0.0;
+    double s2 = 0.0;
 #pragma unroll
     for (int k = 0; k < FIN_IT; ++k) {
         const double sc = q[k].m > -INFINITY ? exp_nonpos_d(q[k].m - M) : 0.0;
-        e[k] = run;
-        run += q[k].s1 * sc;
+        wl[fin_slot(k * FIN_TPB + tid)] = q[k].s1 * sc;
         s2 += q[k].s2 * (sc * sc);
+    }
+    __syncthreads();
+    double e[FIN_IT];
+    double run = 0.0;
+#pragma unroll
+    for (int k = 0; k < FIN_IT; ++k) {
+        e[k] = run;
+        run += wl[fin_slot(tid * FIN_IT + k)];
     }
     const double incl = wave_incl_scan(run);
     const double excl = lane_prev(incl, 0.0);
@@ -215,10 +253,18 @@ __device__ __forceinline__ void normalise_one_pass(const TilePartial *__restrict
     }
     const double lo = lane_id() == 0 ? before : before + excl;
     const double hi = before + incl;
+    // back through LDS (its reads above completed before the two barriers)
+    // for coalesced stores
 #pragma unroll
     for (int k = 0; k < FIN_IT; ++k)
-        if (b0 + k < ntiles)
-            prefix[b0 + k] = fmin(lo + e[k], hi);
+        wl[fin_slot(tid * FIN_IT + k)] = fmin(lo + e[k], hi);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < FIN_IT; ++k) {
+        const int64_t b = (int64_t)k * FIN_TPB + tid;
+        if (b < ntiles)
+            prefix[b] = wl[fin_slot(k * FIN_TPB + tid)];
+    }
     if (tid == 0)
         prefix[ntiles] = total;
     *M_out = M;
@@ -233,6 +279,7 @@ __device__ __forceinline__ void normalise_one_pass(const TilePartial *__restrict
 __device__ __forceinline__ void normalise_block(const Prob &P, int32_t step)
 {
     __shared__ double red[2 * FIN_NW];
+    __shared__ double wl[FIN_LDS];
     const TilePartial *__restrict__ part = P.partials;
     const int64_t ntiles = P.ntiles, n = P.n;
     double *__restrict__ prefix = P.prefix;
@@ -246,7 +293,7 @@ __device__ __forceinline__ void normalise_block(const Prob &P, int32_t step)
     }
     double M, S1, S2;
     if (ntiles <= FIN_PASS) {
-        normalise_one_pass(part, ntiles, prefix, red, &M, &S1, &S2);
+        normalise_one_pass(part, ntiles, prefix, red, wl, &M, &S1, &S2);
     } else {
         double m = -INFINITY;
         for (int64_t b = (int64_t)tid * FIN_IT; b < ntiles; b += FIN_PASS) {
@@ -312,7 +359,7 @@ __device__ __forceinline__ void normalise_block(const Prob &P, int32_t step)
 // estimates of the previous step), independent of the normalisation.
 __device__ __forceinline__ void monitor_block(const Prob &P, const MonDest &md)
 {
-    __shared__ double red[FIN_NW];
+    __shared__ double red[MON_STRIDE * FIN_NW];
     __shared__ double col[MON_STRIDE];
     mon_combine<FIN_TPB>(P.mon, P.ntiles, md, P.hist, P.hist_len, red, col);
 }
@@ -521,13 +568,11 @@ struct TileCdf {
     int lastpos;  // tile-local index of the last positive-weight particle, -1 if none
 };
 
-__device__ __forceinline__ TileCdf tile_cdf(const double *__restrict__ lw, int64_t base, int len,
-                                            double mb, double sc, double Pb, double Pb1,
-                                            double *red, double *wave_last, int *wave_pos)
+// The lane's ITEMS log-weights of the tile (-inf past its end).
+__device__ __forceinline__ void tile_load_lw(const double *__restrict__ lw, int64_t base, int len,
+                                             double (&l)[ITEMS])
 {
-    const int tid = threadIdx.x;
-    const int j0 = ITEMS * tid;
-    double l[ITEMS];
+    const int j0 = ITEMS * threadIdx.x;
     if (j0 + ITEMS <= len) {
         const double4 q = *reinterpret_cast<const double4 *>(lw + base + j0);
         l[0] = q.x;
@@ -539,6 +584,14 @@ __device__ __forceinline__ TileCdf tile_cdf(const double *__restrict__ lw, int64
         for (int k = 0; k < ITEMS; ++k)
             l[k] = j0 + k < len ? lw[base + j0 + k] : -INFINITY;
     }
+}
+
+__device__ __forceinline__ TileCdf tile_cdf(const double (&l)[ITEMS], double mb, double sc,
+                                            double Pb, double Pb1, double *red,
+                                            double *wave_last, int *wave_pos)
+{
+    const int tid = threadIdx.x;
+    const int j0 = ITEMS * tid;
     double a[ITEMS];
     double run = 0.0;
     int lastpos = -1;
@@ -633,7 +686,9 @@ __device__ __forceinline__ void resample_tile(const Prob &P, int64_t b, uint32_t
     const double Pb = prefix[b], Pb1 = prefix[b + 1];
     const double mb = part[b].m;
     const double sc = mb > -INFINITY ? exp_nonpos_d(mb - M) : 0.0;
-    const TileCdf cdf = tile_cdf(lw, base, len, mb, sc, Pb, Pb1, red, wave_last, wave_pos);
+    double l[ITEMS];
+    tile_load_lw(lw, base, len, l);
+    const TileCdf cdf = tile_cdf(l, mb, sc, Pb, Pb1, red, wave_last, wave_pos);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
         sS[ITEMS * tid + k] = cdf.S[k];
@@ -736,16 +791,24 @@ __device__ __forceinline__ void resample_sys_tile(const Prob &P, int64_t b, uint
     __shared__ long long tile_lo;
     __shared__ double sh_U;
     const int tid = threadIdx.x;
-    const bool go = force != 0 || scalars[SMC_S_FLAG] != 0.0;
+    const int64_t base = b * TILE;
+    const int len = (int)min((int64_t)TILE, n - base);
+    // every load of the tile in one round trip: the decision, the
+    // normalisation and the log-weights (the last read in vain on steps that
+    // do not resample)
+    const double flag = scalars[SMC_S_FLAG];
+    const double M = scalars[SMC_S_M];
+    const double stot = prefix[ntiles];
+    const double Pb = prefix[b], Pb1 = prefix[b + 1];
+    const double mb = P.partials[b].m;
+    double l[ITEMS];
+    tile_load_lw(lw, base, len, l);
+    const bool go = force != 0 || flag != 0.0;
     if (!go) {
         if (b == 0 && tid == 0)
             scalars[SMC_S_RESAMPLED] = 0.0;
         return;
     }
-    const int64_t base = b * TILE;
-    const int len = (int)min((int64_t)TILE, n - base);
-    const double M = scalars[SMC_S_M];
-    const double stot = prefix[ntiles];
     if (!(stot > 0.0) || !isfinite(stot) || !isfinite(M)) {
         if (b == 0 && tid == 0) {
             atomicOr(&P.counters[CNT_ERR], SMC_DEVERR_ZERO_WEIGHTS);
@@ -753,15 +816,13 @@ __device__ __forceinline__ void resample_sys_tile(const Prob &P, int64_t b, uint
         }
         return;
     }
-    const double Pb = prefix[b], Pb1 = prefix[b + 1];
-    const double mb = P.partials[b].m;
     const double sc = mb > -INFINITY ? exp_nonpos_d(mb - M) : 0.0;
     // the step's systematic offset: one lane draws it while the tile loads
     if (tid == 0) {
         const uint4 wU = draw(P.key, 0, t, TAG_RESAMPLE, 0, P.problem_id);
         sh_U = u53(wU.x, wU.y);
     }
-    const TileCdf cdf = tile_cdf(lw, base, len, mb, sc, Pb, Pb1, red, wave_last, wave_pos);
+    const TileCdf cdf = tile_cdf(l, mb, sc, Pb, Pb1, red, wave_last, wave_pos);
     const double U = sh_U;  // tile_cdf ends on a barrier
     const double nd = (double)n;
     const double r = nd / stot;
@@ -1074,7 +1135,7 @@ __global__ __launch_bounds__(FIN_TPB) void mon_final_kernel(const double *__rest
                                                             double *__restrict__ hist,
                                                             int64_t hist_len)
 {
-    __shared__ double red[FIN_NW];
+    __shared__ double red[MON_STRIDE * FIN_NW];
     __shared__ double col[MON_STRIDE];
     mon_combine<FIN_TPB>(mon, ntiles, md, hist, hist_len, red, col);
 }
