@@ -51,7 +51,8 @@ def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="pf",
-                    choices=["pf", "pf-c0", "gmm-c2", "gmm-c3", "batch", "copy", "study"])
+                    choices=["pf", "pf-c0", "gmm-c2", "gmm-c3", "batch", "models", "copy",
+                             "study"])
     ap.add_argument("--steps", type=int, default=189)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=1 << 22)
@@ -65,6 +66,7 @@ def _parse():
     ap.add_argument("--variants", action="store_true",
                     help="also time the FP32-state and multinomial variants")
     ap.add_argument("--tune", action="store_true", help="batch: run the autotuner first")
+    ap.add_argument("--model-seeds", type=int, default=4, help="models: seeds per K")
     ap.add_argument("--study-problem", default="c2", choices=["c2", "c3"])
     ap.add_argument("--study-methods", default="mala,rw,rw:0.05")
     ap.add_argument("--study-tol", type=float, default=0.05)
@@ -357,6 +359,7 @@ def bench_gmm(args):
                      "avg_launch_ms": avg_ms, "terms_per_launch": terms_per_launch},
         "terms_per_s": terms_per_launch / (avg_ms * 1e-3),
         "log_z": logz,
+        "log_z_path_sampling": s.log_z_path(),
         "accept_rate": (hist[1:, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3].sum(axis=0) / (n * T)).tolist(),
         "resamples": int(hist[1:, L.SMC_H_FLAG].sum()),
     }
@@ -405,6 +408,54 @@ def bench_batch(args):
     }
     br.close()
     return out
+
+
+# ------------------------------------------- model comparison over K (batched)
+
+def bench_models(args):
+    """Bayesian model comparison over the number of mixture components
+    (Section 5.2: the evidence p(y | M_r) of every r = 1..8 on the
+    four-component data of the random-walk sampler, several seeds each),
+    all samplers advanced together as one batched HIP graph per step.
+    Posterior model probabilities assume a uniform prior over r."""
+    import torch
+    import synth
+    import paper_1306_5583_amd as pkg
+    y = synth.gmm_data_four_components(1000, synth.DATA_SEED[2])
+    T, n = 100, 1 << 14
+    alphas = synth.prior_tempering(T, 4.0)
+    Ks = list(range(1, 9))
+    seeds = list(range(1, args.model_seeds + 1))
+    specs = [pkg.GmmSpec(n=n, y=y, K=K, alphas=alphas, move="rw", seed=s,
+                         problem_id=100 * K + s) for K in Ks for s in seeds]
+    br = pkg.BatchRunner(specs)
+    br.run(2, graph=True)          # warm-up (graph capture included)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat = np.array(br.run(T, graph=True, latencies=True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    br.check()
+    logz = np.array([br.log_z(i) for i in range(len(specs))]).reshape(len(Ks), len(seeds))
+    mean = logz.mean(axis=1)
+    se = logz.std(axis=1, ddof=1) / np.sqrt(len(seeds)) if len(seeds) > 1 else np.zeros(len(Ks))
+    post = np.exp(mean - mean.max())
+    post /= post.sum()
+    br.close()
+    parts = n * len(specs)
+    return {
+        "metric": METRIC, "value": parts * T / wall, "unit": METRIC, "n_gpus": 1,
+        "steps": T, "warmup": 2, "ms_per_step": 1e3 * wall / T, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "model comparison: random-walk mixture samplers for K=1..8 "
+                               "(x%d seeds), n=1000 four-component data, N=2^14 each, T=100, "
+                               "alpha=(t/T)^4, one batched HIP graph per step" % len(seeds),
+                   "K": Ks, "seeds": len(seeds), "n": n, "T": T},
+        "log_z": {str(K): float(m) for K, m in zip(Ks, mean)},
+        "log_z_se": {str(K): float(e) for K, e in zip(Ks, se)},
+        "posterior_K": {str(K): float(p) for K, p in zip(Ks, post)},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+    }
 
 
 # ------------------------------------------------- MALA vs random walk study
@@ -512,9 +563,8 @@ def bench_copy(args):
 def main():
     args = _parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); "
-              "multi-GPU sharding is described in DESIGN.md but not implemented" % args.gpus,
-              file=sys.stderr)
+        print("bench.py: one GPU only (--gpus %d requested); the sweep is not sharded "
+              "across GPUs" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -528,6 +578,8 @@ def main():
         out = bench_gmm(args)
     elif args.workload == "batch":
         out = bench_batch(args)
+    elif args.workload == "models":
+        out = bench_models(args)
     elif args.workload == "study":
         out = bench_study(args)
     else:

@@ -97,6 +97,9 @@ enum {
     SMC_S_RESAMPLED = 8,/* 1 when the last resample call produced new ancestors */
     SMC_S_U = 9,        /* systematic offset U of the last resample */
     SMC_S_LPRE = 10,    /* L before the last resample (diagnostic) */
+    SMC_S_PS_LOGZ = 11, /* GMM: running path-sampling log Z (trapezoid over alpha) */
+    SMC_S_PS_U = 12,    /* GMM: U of the last monitored step */
+    SMC_S_PS_ALPHA = 13,/* GMM: alpha of the last monitored step (-1: none yet) */
     SMC_SCALARS_LEN = 16
 };
 
@@ -112,6 +115,7 @@ enum {
     SMC_H_ACC2 = 7,
     SMC_H_PATH = 8, /* GMM: U_t = sum_i W_i l_i (path-sampling integrand) */
     SMC_H_MON = 9,  /* CV: importance-sampling means of the 4 state rows (cols 9..12) */
+    SMC_H_PS = 13,  /* GMM: path-sampling log Z after this step's monitor */
     SMC_HIST_COLS = 16
 };
 
@@ -238,7 +242,15 @@ smc_status smc_resample(smc_ctx *ctx, int32_t step, int32_t force);
  * monitors) of every state row under the current normalised weights,
  * written to history row `step` (CV: columns SMC_H_MON..; GMM: column
  * SMC_H_PATH gets sum W l) and, when out_dev is non-NULL, to out_dev[rows]
- * (device pointer). */
+ * (device pointer).
+ * GMM: the same call advances the path-sampling estimate of log Z
+ * (Section 5.2, path sampling: log Z = integral over alpha of E_alpha[l]) by
+ * the trapezoid from the previously monitored step to this one, using the
+ * alpha of the last smc_move (0 before any move):
+ *   PS += (alpha - alpha_prev) (U + U_prev) / 2,
+ * kept in scalars SMC_S_PS_LOGZ and history column SMC_H_PS.  The first
+ * monitored step only records (alpha, U); monitoring step 0 (after smc_init
+ * and smc_ess) and every step makes the sum run over the whole schedule. */
 smc_status smc_monitor(smc_ctx *ctx, int32_t step, double *out_dev);
 
 /* Applies pending ancestors to the state (the value-collection copy of

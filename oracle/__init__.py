@@ -109,6 +109,7 @@ def _declare(L):
         "orc_gmm_block_trace": (_i32, [ctypes.POINTER(GmmCfg), _u32, _i32, _i32, _d, _d, _dp,
                                        _i64, _dp, _dp, _dp, _dp, _ip, _dp, _dp]),
         "orc_gmm_run": (_d, [ctypes.POINTER(GmmCfg), _dp, _i64, _i32, _dp, _dp, _dp, _dp, _dp]),
+        "orc_path_sampling": (_d, [_dp, _dp, _i64]),
     }
     for name, (res, args) in list(sig.items()) + list(gmm_sig.items()):
         if not hasattr(L, name):
@@ -222,6 +223,15 @@ def resample(scheme, seed, t, lw, p=0):
     if rc != 0:
         raise FloatingPointError("all weights zero or non-finite")
     return anc, S, u
+
+
+def path_sampling(alpha, U):
+    """Trapezoid of Eq. path_est over the schedule alpha[0..T] with the
+    integrands U[0..T] (Section 5.2, path sampling): the sum over t of
+    (alpha_t - alpha_{t-1}) (U_t + U_{t-1}) / 2."""
+    a = _f64(alpha)
+    u = _f64(U)
+    return float(lib().orc_path_sampling(_d_ptr(a), _d_ptr(u), a.size))
 
 
 def copy_from(anc):
@@ -395,14 +405,17 @@ def gmm_block_trace(cfg, t, block, sweep, alpha, scale, y, pop, ll, lp, grad=Non
 
 
 def gmm_run(cfg, y, alpha, scales):
-    """Whole sampler; returns (logZ, hist[T+1][9], pop_final, lw_final).
+    """Whole sampler (Algorithm "gmm"); returns (logZ, hist[T+1][10],
+    pop_final, lw_final).
 
-    hist columns: ESS, resampled, dlogZ, logZ, L, accepts(mu, eta, z), U_t."""
+    hist columns: ESS, resampled, dlogZ, logZ (Eq. smc-ds), L,
+    accepts(mu, eta, z), U_t (Eq. path_import) and the running path-sampling
+    estimate (Eq. path_est)."""
     y = _f64(y)
     alpha = _f64(alpha)
     T = alpha.size - 1
     scales = _f64(scales).reshape(T + 1, 3)
-    hist = np.zeros((T + 1, 9))
+    hist = np.zeros((T + 1, 10))
     D = 3 * cfg.K - 1
     pop = np.zeros((D, cfg.n))
     lwf = np.zeros(cfg.n)

@@ -34,6 +34,8 @@ typedef struct {
 } orc_gmm_cfg;
 
 static const double LOG_2PI = 1.8378770664093454835606594728112;
+/* columns of the per-step record of orc_gmm_run */
+#define ORC_GMM_HIST_COLS 10
 
 /* log omega_j for j = 0..K-1 from the K-1 logits (reference component K). */
 static void log_weights(const double *z, int K, double *logw)
@@ -363,6 +365,18 @@ int32_t orc_gmm_block_trace(const orc_gmm_cfg *c, uint32_t t, int32_t block, int
  * path_import).  Final population written to pop_final / ll / lp / lw when
  * non-NULL.  Returns the direct estimate log Z (Eq. smc-ds).
  */
+/* Path-sampling estimate of log(Z_1 / Z_0) (Section 5.2, Eq. path_est): the
+   trapezoidal rule over the annealing schedule alpha[0..T] applied to the
+   importance-sampling integrands U[0..T] (Eq. path_import), summed in t
+   order. */
+double orc_path_sampling(const double *alpha, const double *U, int64_t len)
+{
+    double ps = 0.0;
+    for (int64_t t = 1; t < len; ++t)
+        ps += 0.5 * (alpha[t] - alpha[t - 1]) * (U[t] + U[t - 1]);
+    return ps;
+}
+
 double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
                    const double *alpha, const double *scales, double *hist, double *pop_final,
                    double *lw_final)
@@ -388,11 +402,18 @@ double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
         }
     double logZ = 0.0, Lprev = log((double)n), a_prev = 0.0;
     int resampled = 0;
+    /* path sampling (Section 5.2, Eq. path_est): U_0 is the plain average of
+       the log-likelihood over the prior draws (equal weights) */
+    orc_ksum u0 = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i)
+        orc_ks_add(&u0, ll[i]);
+    double U_prev = orc_ks_val(&u0) / (double)n, ps = 0.0, a_alpha_prev_ps = 0.0;
     if (hist) {
-        for (int q = 0; q < 9; ++q)
+        for (int q = 0; q < ORC_GMM_HIST_COLS; ++q)
             hist[q] = 0.0;
         hist[0] = (double)n;
         hist[4] = Lprev;
+        hist[8] = U_prev;
     }
     for (int32_t t = 1; t <= T; ++t) {
         double a = alpha[t];
@@ -435,8 +456,19 @@ double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
             for (int b = 0; b < 3; ++b)
                 acc[b] += gmm_block_impl(c, (uint32_t)t, b, s, a, scales[3 * t + b], y, nd, pop,
                                          ll, lp, grad, NULL, NULL, NULL);
+        /* U_t = sum_i W_t^(i) l(theta_t^(i)) (Eq. path_import: under the
+           geometric path the integrand d log q_alpha / d alpha is the
+           log-likelihood) and one trapezoid of Eq. path_est */
+        double L = resampled ? log((double)n) : nz[0];
+        orc_ksum u = {0.0, 0.0};
+        for (int64_t i = 0; i < n; ++i)
+            orc_ks_add(&u, exp(lw[i] - L) * ll[i]);
+        const double U = orc_ks_val(&u);
+        ps += 0.5 * (a - a_alpha_prev_ps) * (U + U_prev);
+        U_prev = U;
+        a_alpha_prev_ps = a;
         if (hist) {
-            double *h = hist + 9 * (int64_t)t;
+            double *h = hist + ORC_GMM_HIST_COLS * (int64_t)t;
             h[0] = nz[2];
             h[1] = resampled;
             h[2] = dlogz;
@@ -445,11 +477,8 @@ double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
             h[5] = acc[0];
             h[6] = acc[1];
             h[7] = acc[2];
-            double L = resampled ? log((double)n) : nz[0];
-            orc_ksum u = {0.0, 0.0};
-            for (int64_t i = 0; i < n; ++i)
-                orc_ks_add(&u, exp(lw[i] - L) * ll[i]);
-            h[8] = orc_ks_val(&u);
+            h[8] = U;
+            h[9] = ps;
         }
     }
     if (pop_final)

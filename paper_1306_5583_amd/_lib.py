@@ -28,10 +28,11 @@ SCHEMES = {"multinomial": SMC_RS_MULTINOMIAL, "systematic": SMC_RS_SYSTEMATIC,
 
 # scalar block and history layout
 (SMC_S_L, SMC_S_L2, SMC_S_LOGZ, SMC_S_ESS, SMC_S_DLOGZ, SMC_S_FLAG, SMC_S_M, SMC_S_STOT,
- SMC_S_RESAMPLED, SMC_S_U, SMC_S_LPRE) = range(11)
+ SMC_S_RESAMPLED, SMC_S_U, SMC_S_LPRE, SMC_S_PS_LOGZ, SMC_S_PS_U, SMC_S_PS_ALPHA) = range(14)
 SMC_SCALARS_LEN = 16
 (SMC_H_ESS, SMC_H_FLAG, SMC_H_DLOGZ, SMC_H_LOGZ, SMC_H_L, SMC_H_ACC0, SMC_H_ACC1, SMC_H_ACC2,
  SMC_H_PATH, SMC_H_MON) = range(10)
+SMC_H_PS = 13
 SMC_HIST_COLS = 16
 SMC_DEVERR_ZERO_WEIGHTS, SMC_DEVERR_NONFINITE, SMC_DEVERR_GAMMA = 1, 2, 4
 

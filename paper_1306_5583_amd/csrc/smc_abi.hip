@@ -413,6 +413,7 @@ smc_status smc_init(smc_ctx *ctx)
     Ctx &c = ctx->c;
     c.cur = 0;
     c.armed_lw = c.armed_gather = false;
+    c.last_alpha = 0.0;
     hipError_t e = launch_reset_scalars(c);
     if (e == hipSuccess)
         e = c.cfg.model == SMC_MODEL_CV_TRACK ? launch_pf_init(c) : launch_gmm_init(c);
@@ -465,6 +466,7 @@ smc_status smc_move(smc_ctx *ctx, int32_t step, const smc_move_args *args)
             return fail(c, SMC_ERR_INVALID_ARG, "sweeps must be in [0, 64]");
         e = launch_gmm_move(c, step, *args, c.armed_gather);
         c.armed_gather = false;
+        c.last_alpha = args->alpha;
     }
     return hip_status(c, e, "smc_move");
 }

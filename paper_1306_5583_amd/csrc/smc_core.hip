@@ -30,6 +30,7 @@ __global__ void reset_scalars_kernel(double *scalars, int32_t *counters, int64_t
         scalars[SMC_S_L] = log((double)n);
         scalars[SMC_S_L2] = log((double)n);
         scalars[SMC_S_ESS] = (double)n;
+        scalars[SMC_S_PS_ALPHA] = -1.0;
     }
 }
 
@@ -122,6 +123,8 @@ struct MonDest {
     int hist_col;     // first history column receiving estimates
     int hist_ncols;   // how many of the last rows go to the history
     double *out;      // optional device output [rows]
+    double *scalars;  // mixture sampler: path-sampling accumulator (else null)
+    double alpha;     // tempering exponent of the monitored particles
 };
 
 // Sums the tile partials of every monitored row with the whole workgroup:
@@ -181,6 +184,20 @@ __device__ void mon_combine(const double *__restrict__ mon, int64_t ntiles, cons
         if (hist && d.step >= 0 && d.step < hist_len && r >= d.rows - d.hist_ncols)
             hist[(int64_t)d.step * SMC_HIST_COLS + d.hist_col + (r - (d.rows - d.hist_ncols))] =
                 est;
+        // path sampling (Section 5.2): the last row is U = sum W l at alpha;
+        // one trapezoid from the previously monitored (alpha, U)
+        if (d.scalars && r == d.rows - 1) {
+            double *sc = d.scalars;
+            const double a0 = sc[SMC_S_PS_ALPHA];
+            double ps = sc[SMC_S_PS_LOGZ];
+            if (a0 >= 0.0)
+                ps += 0.5 * (d.alpha - a0) * (est + sc[SMC_S_PS_U]);
+            sc[SMC_S_PS_LOGZ] = ps;
+            sc[SMC_S_PS_U] = est;
+            sc[SMC_S_PS_ALPHA] = d.alpha;
+            if (hist && d.step >= 0 && d.step < hist_len)
+                hist[(int64_t)d.step * SMC_HIST_COLS + SMC_H_PS] = ps;
+        }
     }
 }
 
@@ -390,6 +407,8 @@ __global__ __launch_bounds__(FIN_TPB) void finalize_batch_kernel(const Prob *__r
         return;
     MonDest md;
     md.out = nullptr;
+    md.scalars = nullptr;
+    md.alpha = 0.0;
     md.rows = FIN_MON_ROWS;
     md.hist_col = SMC_H_MON;
     md.hist_ncols = FIN_MON_ROWS;
@@ -448,12 +467,16 @@ static MonDest mon_dest(const Ctx &c, int32_t step, int rows, double *out)
     d.step = step;
     d.rows = rows;
     d.out = out;
+    d.scalars = nullptr;
+    d.alpha = 0.0;
     if (c.cfg.model == SMC_MODEL_CV_TRACK) {
         d.hist_col = SMC_H_MON;
         d.hist_ncols = rows;
     } else {
         d.hist_col = SMC_H_PATH;  // the last monitored row is the log-likelihood
         d.hist_ncols = 1;
+        d.scalars = c.buf.scalars;
+        d.alpha = c.last_alpha;
     }
     return d;
 }

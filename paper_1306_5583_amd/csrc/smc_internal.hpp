@@ -115,6 +115,9 @@ struct Ctx {
     // flag) has not yet been applied to the log-weights / the state.
     bool armed_lw = false;
     bool armed_gather = false;
+    // Tempering exponent of the last mixture move (the path-sampling abscissa
+    // of the next monitor).
+    double last_alpha = 0.0;
     // Monitor partials produced by a move for an earlier step, completed by
     // the next normalisation (-1: none pending).
     int32_t mon_pending_step = -1;

@@ -194,9 +194,15 @@ class GmmSampler(_Base):
         self.alpha_prev = 0.0
         self.monitor_out = torch.zeros(self.D + 1, dtype=torch.float64, device=self.device)
 
-    def init(self):
+    def init(self, monitor: bool = True):
+        """Prior draws (alpha = 0).  With `monitor` the initial population is
+        normalised and monitored as step 0, the first point of the
+        path-sampling estimate."""
         L.smc_init(self.ctx)
         self.alpha_prev = 0.0
+        if monitor:
+            L.smc_ess(self.ctx, 0)
+            L.smc_monitor(self.ctx, 0, self.monitor_out.data_ptr())
 
     def step(self, t: int, alpha: float, scales=None, monitor: bool = True):
         """Iteration t of Algorithm 'gmm' at tempering exponent alpha."""
@@ -220,10 +226,16 @@ class GmmSampler(_Base):
     def run(self, alphas, scales=None, monitor: bool = True) -> float:
         """alphas[0..T] with alphas[0] = 0; scales[t] per block or None for
         the default schedule."""
-        self.init()
+        self.init(monitor)
         for t in range(1, len(alphas)):
             self.step(t, float(alphas[t]), None if scales is None else scales[t], monitor)
         return self.log_z()
+
+    def log_z_path(self) -> float:
+        """Path-sampling estimate of log Z (Section 5.2): the trapezoid over
+        the monitored tempering exponents of U_t = sum_i W_i l(theta_i),
+        accumulated on the device by each monitor call."""
+        return self.scalars_host()[L.SMC_S_PS_LOGZ]
 
     def history_host(self) -> np.ndarray:
         torch.cuda.synchronize(self.device)

@@ -237,3 +237,29 @@ def test_full_size_batched_workload_sampled(lib, orc):
     logz_o, hist_o, _, _ = orc.pf_run(orc.pf_cfg(kw["n"], kw["seed"], problem=small),
                                       kw["y"][:steps + 1])
     assert abs(br.log_z(small) - logz_o) <= 1e-12 * max(1.0, np.abs(hist_o[:, 2]).sum())
+
+
+def test_model_comparison_over_k(lib):
+    # Section 5.2's purpose for the mixture example: the evidence of M_r for
+    # several r from one batched run.  Data from two well-separated
+    # components: one component explains them far worse (the gap is hundreds
+    # of nats), and every batched evidence equals its single-problem run.
+    pkg, L = lib
+    y = synth.gmm_data(200, [-4.0, 4.0], 4.0, [0.5, 0.5], 77)
+    T = 30
+    alphas = synth.prior_tempering(T, 4.0)
+    Ks = [1, 2, 3]
+    specs = [pkg.GmmSpec(n=1 << 12, y=y, K=K, alphas=alphas, move="rw", seed=3,
+                         problem_id=K) for K in Ks]
+    br = pkg.BatchRunner(specs)
+    br.run(T, graph=True)
+    br.check()
+    logz = [br.log_z(i) for i in range(len(Ks))]
+    assert logz[1] - logz[0] > 100.0, logz
+    for i, K in enumerate(Ks):
+        s = pkg.GmmSampler(1 << 12, y, K, T, seed=3, problem_id=K, move="rw")
+        s.run(alphas)
+        scale = max(1.0, np.abs(s.history_host()[:, L.SMC_H_DLOGZ]).sum())
+        assert abs(logz[i] - s.log_z()) <= 1e-10 * scale, (K, logz[i], s.log_z())
+        s.close()
+    br.close()

@@ -190,6 +190,14 @@ def test_end_to_end_small(lib, orc):
     assert np.array_equal(hist[1:, L.SMC_H_FLAG], hist_o[1:, 1])
     acc_g = hist[1:, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3]
     assert np.all(np.abs(acc_g - hist_o[1:, 5:8]) <= 2)
+    # path sampling: the integrands U_0..U_T (step 0 = the prior draws) and
+    # the running trapezoid, against the oracle's
+    U_g, U_o = hist[:, L.SMC_H_PATH], hist_o[:, 8]
+    assert np.all(np.abs(U_g - U_o) <= 1e-9 * np.maximum(1.0, np.abs(U_o)))
+    ps_scale = max(1.0, float(np.sum(0.5 * np.diff(alphas) * (np.abs(U_o[1:]) + np.abs(U_o[:-1])))))
+    assert np.all(np.abs(hist[:, L.SMC_H_PS] - hist_o[:, 9]) <= 1e-9 * ps_scale)
+    assert abs(s.log_z_path() - hist_o[T, 9]) <= 1e-9 * ps_scale
+    assert s.log_z_path() == hist[T, L.SMC_H_PS]
     s.check()
 
 

@@ -206,3 +206,60 @@ def test_k1_evidence_matches_quadrature(orc, move):
     vals = np.array(vals)
     se = vals.std(ddof=1) / math.sqrt(vals.size)
     assert abs(vals.mean() - ref) < 4 * se + 0.02, (vals.mean(), ref, se)
+
+
+def _conjugate_path(y, alpha):
+    """E_alpha[log N(y | theta, 1)] under q_alpha = N(theta | 0, 1) N(y |
+    theta, 1)^alpha: theta ~ N(alpha y / (1 + alpha), 1 / (1 + alpha))."""
+    a = np.asarray(alpha, dtype=float)
+    m = a * y / (1.0 + a)
+    v = 1.0 / (1.0 + a)
+    return -0.5 * math.log(2 * math.pi) - 0.5 * ((y - m) ** 2 + v)
+
+
+@pytest.mark.parametrize("power", [1.0, 4.0])
+def test_path_sampling_trapezoid_closed_form(orc, power):
+    # Eq. path_identity on a conjugate Gaussian: log Z = log N(y | 0, 2); the
+    # trapezoid of Eq. path_est converges at O(1/T^2), and since E_alpha[l]
+    # increases with alpha (its derivative is a variance) the error is at
+    # most half the spread between the left and right Riemann sums
+    y = 1.7
+    exact = stats.norm.logpdf(y, 0.0, math.sqrt(2.0))
+    errs = []
+    for T in (25, 50, 100, 200):
+        alpha = synth.prior_tempering(T, power)
+        U = _conjugate_path(y, alpha)
+        ps = orc.path_sampling(alpha, U)
+        bound = 0.5 * float(np.sum(np.diff(alpha) * np.diff(U)))
+        assert abs(ps - exact) <= bound + 1e-14
+        errs.append(abs(ps - exact))
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all((ratios > 3.5) & (ratios < 4.5)), ratios
+
+
+def test_path_sampling_matches_direct_estimate_k1(orc):
+    # the sampler's own U_t: path sampling and the direct estimate both reach
+    # the quadrature evidence of a one-component model, the former up to its
+    # trapezoid error (bounded as above, from the seed-averaged integrands)
+    y = synth.gmm_data(30, [1.0], 2.0, [1.0], 99)
+    ref = gmm_k1_log_evidence(y, 0.0, 10.0, 1.0, 1.0)
+    T = 40
+    alpha = synth.prior_tempering(T, 4.0)
+    scales = np.array([rw_scales(a) for a in alpha])
+    ps, ds, us = [], [], []
+    for seed in range(1, 9):
+        cfg = orc.gmm_cfg(1 << 12, seed, 1)
+        logz, hist, _, _ = orc.gmm_run(cfg, y, alpha, scales)
+        ds.append(logz)
+        ps.append(hist[T, 9])
+        us.append(hist[:, 8])
+        # the recorded running value is the trapezoid of the recorded U
+        assert hist[T, 9] == pytest.approx(orc.path_sampling(alpha, hist[:, 8]), abs=1e-9)
+        assert np.all(np.diff(hist[:, 9][1:]) == pytest.approx(
+            0.5 * np.diff(alpha)[1:] * (hist[2:, 8] + hist[1:-1, 8]), abs=1e-9))
+    ps, ds = np.array(ps), np.array(ds)
+    ubar = np.mean(us, axis=0)
+    bound = 0.5 * float(np.sum(np.diff(alpha) * np.abs(np.diff(ubar))))
+    se = ps.std(ddof=1) / math.sqrt(ps.size)
+    assert abs(ps.mean() - ref) <= bound + 4 * se + 0.02, (ps.mean(), ref, bound, se)
+    assert abs(ds.mean() - ref) < 4 * ds.std(ddof=1) / math.sqrt(ds.size) + 0.02
