@@ -258,6 +258,19 @@ smc_status smc_monitor(smc_ctx *ctx, int32_t step, double *out_dev);
  * population.  No-op when nothing is pending. */
 smc_status smc_gather(smc_ctx *ctx);
 
+/* In-place parent layout of the value-collection copy (Section 4.1,
+ * copy(N, copy_from)) for the ancestors of the last resample call:
+ * copy_from_dev[j] = j for every particle j with offspring, and the
+ * particles without offspring, in ascending order, take the extra copies in
+ * ascending (parent, copy) order, so that applying
+ * x[j] <- x[copy_from[j]] in place needs no second buffer.  Writes the
+ * identity when the last resample call did not resample (device decision).
+ * copy_from_dev: device int32[n], caller-owned; enqueued on the context's
+ * stream (uses the workspace, so calls on one context must not overlap).
+ * Errors: SMC_ERR_INVALID_ARG (null pointer), SMC_ERR_BAD_STATE (before
+ * smc_init), SMC_ERR_DEVICE (launch failure). */
+smc_status smc_copy_from(smc_ctx *ctx, int32_t *copy_from_dev);
+
 /* Device pointer of the buffer that currently holds the state. */
 smc_status smc_current_state(smc_ctx *ctx, void **state);
 

@@ -114,6 +114,7 @@ def load() -> ctypes.CDLL:
         "smc_resample": (st, [_vp, _i32, _i32]),
         "smc_monitor": (st, [_vp, _i32, _vp]),
         "smc_gather": (st, [_vp]),
+        "smc_copy_from": (st, [_vp, _vp]),
         "smc_current_state": (st, [_vp, P(_vp)]),
         "smc_read_scalars": (st, [_vp, P(_d)]),
         "smc_check": (st, [_vp]),
@@ -146,7 +147,7 @@ def load() -> ctypes.CDLL:
 def exported_symbols():
     return ["smc_status_string", "smc_state_rows", "smc_workspace_size", "smc_create",
             "smc_destroy", "smc_set_stream", "smc_init", "smc_move", "smc_reweight", "smc_ess",
-            "smc_resample", "smc_monitor", "smc_gather", "smc_current_state",
+            "smc_resample", "smc_monitor", "smc_gather", "smc_copy_from", "smc_current_state",
             "smc_read_scalars", "smc_check", "smc_last_error", "smc_gmm_loglik_grad",
             "smc_draw_words", "smc_profile_start", "smc_profile_read", "smc_batch_table_size", "smc_batch_create", "smc_batch_destroy",
             "smc_batch_autotune", "smc_batch_waves", "smc_batch_init", "smc_batch_step",
@@ -253,6 +254,10 @@ def smc_monitor(ctx, step, out_ptr=None):
 
 def smc_gather(ctx):
     _check(load().smc_gather(ctx), "smc_gather", ctx)
+
+
+def smc_copy_from(ctx, out_ptr):
+    _check(load().smc_copy_from(ctx, out_ptr), "smc_copy_from", ctx)
 
 
 def smc_current_state(ctx):

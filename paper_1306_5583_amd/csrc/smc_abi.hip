@@ -49,6 +49,10 @@ Workspace plan_workspace(const smc_config &cfg)
     }
     w.counters = off;
     off = align256(off + sizeof(int32_t) * 16);
+    w.cf = off;
+    off = align256(off + sizeof(int32_t) * 2 * (size_t)n);
+    w.cf_tiles = off;
+    off = align256(off + sizeof(double) * (size_t)(4 * ntiles + 2));
     if (cfg.scheme == SMC_RS_MULTINOMIAL) {
         w.g = off;
         off = align256(off + sizeof(double) * (size_t)(n + 1));
@@ -577,6 +581,16 @@ smc_status smc_gather(smc_ctx *ctx)
         c.armed_gather = false;
     }
     return hip_status(c, e, "smc_gather");
+}
+
+smc_status smc_copy_from(smc_ctx *ctx, int32_t *copy_from_dev)
+{
+    if (!ctx || !copy_from_dev)
+        return SMC_ERR_INVALID_ARG;
+    Ctx &c = ctx->c;
+    if (!c.initialised)
+        return fail(c, SMC_ERR_BAD_STATE, "smc_copy_from before smc_init");
+    return hip_status(c, launch_copy_from(c, copy_from_dev), "smc_copy_from");
 }
 
 smc_status smc_current_state(smc_ctx *ctx, void **state)

@@ -1227,6 +1227,188 @@ hipError_t launch_gather(Ctx &c)
 }
 
 // ---------------------------------------------------------------------------
+// In-place parent layout of the value-collection copy (Section 4.1,
+// copy(N, copy_from)): every particle with offspring keeps its own index,
+// copy_from[j] = j, and the indices of the particles without offspring, in
+// ascending order, receive the extra copies in ascending (parent, copy)
+// order.  With the sorted ancestors a those extra copies are exactly the
+// slots i > 0 with a_i == a_{i-1}, in slot order.  So: mark the particles
+// that appear (at the first slot of each run of equal ancestors), rank the
+// duplicate slots and the empty particles by exclusive scans over tiles,
+// scatter each duplicate's parent to its rank, and let every empty particle
+// take the parent of the same rank.  Without a resample (device flag 0) the
+// layout is the identity.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void cf_clear_kernel(const double *__restrict__ scalars,
+                                                       int32_t *__restrict__ present, int64_t n)
+{
+    if (scalars[SMC_S_RESAMPLED] == 0.0)
+        return;
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i < n)
+        present[i] = 0;
+}
+
+// Slot tile b: marks the parents of the run starts, counts the duplicates.
+__global__ __launch_bounds__(TPB) void cf_mark_kernel(const double *__restrict__ scalars,
+                                                      const int32_t *__restrict__ anc, int64_t n,
+                                                      int32_t *__restrict__ present,
+                                                      double *__restrict__ cnt_dup)
+{
+    __shared__ double red[NWAVES];
+    if (scalars[SMC_S_RESAMPLED] == 0.0)
+        return;
+    const int64_t base = (int64_t)blockIdx.x * TILE + ITEMS * threadIdx.x;
+    double dups = 0.0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t i = base + k;
+        if (i < n) {
+            const int32_t a = anc[i];
+            if (i == 0 || anc[i - 1] != a)
+                present[a] = 1;
+            else
+                dups += 1.0;
+        }
+    }
+    dups = block_sum<NWAVES>(dups, red);
+    if (threadIdx.x == 0)
+        cnt_dup[blockIdx.x] = dups;
+}
+
+// Particle tile b: counts the particles without offspring.
+__global__ __launch_bounds__(TPB) void cf_count_empty_kernel(const double *__restrict__ scalars,
+                                                             const int32_t *__restrict__ present,
+                                                             int64_t n,
+                                                             double *__restrict__ cnt_empty)
+{
+    __shared__ double red[NWAVES];
+    if (scalars[SMC_S_RESAMPLED] == 0.0)
+        return;
+    const int64_t base = (int64_t)blockIdx.x * TILE + ITEMS * threadIdx.x;
+    double e = 0.0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+        if (base + k < n && present[base + k] == 0)
+            e += 1.0;
+    e = block_sum<NWAVES>(e, red);
+    if (threadIdx.x == 0)
+        cnt_empty[blockIdx.x] = e;
+}
+
+// One workgroup: exclusive tile offsets of both counts (integer-valued, so
+// exact in double precision).
+__global__ __launch_bounds__(FIN_TPB) void cf_scan_kernel(const double *__restrict__ scalars,
+                                                          const double *__restrict__ cnt_dup,
+                                                          const double *__restrict__ cnt_empty,
+                                                          int64_t ntiles,
+                                                          double *__restrict__ off_dup,
+                                                          double *__restrict__ off_empty)
+{
+    __shared__ double red[2 * FIN_NW];
+    if (scalars[SMC_S_RESAMPLED] == 0.0)
+        return;
+    tile_offsets(ntiles, [&](int64_t b) { return cnt_dup[b]; }, off_dup, red);
+    __syncthreads();
+    tile_offsets(ntiles, [&](int64_t b) { return cnt_empty[b]; }, off_empty, red);
+}
+
+// Slot tile b: each duplicate slot writes its parent at its rank.
+__global__ __launch_bounds__(TPB) void cf_dup_kernel(const double *__restrict__ scalars,
+                                                     const int32_t *__restrict__ anc, int64_t n,
+                                                     const double *__restrict__ off_dup,
+                                                     int32_t *__restrict__ dup_parent)
+{
+    __shared__ double red[NWAVES];
+    if (scalars[SMC_S_RESAMPLED] == 0.0)
+        return;
+    const int64_t base = (int64_t)blockIdx.x * TILE + ITEMS * threadIdx.x;
+    int32_t a[ITEMS];
+    bool dup[ITEMS];
+    double run = 0.0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t i = base + k;
+        a[k] = i < n ? anc[i] : 0;
+        dup[k] = i < n && i > 0 && anc[i - 1] == a[k];
+        run += dup[k] ? 1.0 : 0.0;
+    }
+    double total;
+    double r = block_excl_scan<NWAVES>(run, red, &total) + off_dup[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+        if (dup[k]) {
+            dup_parent[(int64_t)r] = a[k];
+            r += 1.0;
+        }
+}
+
+// Particle tile b: the layout itself.
+__global__ __launch_bounds__(TPB) void cf_final_kernel(const double *__restrict__ scalars,
+                                                       const int32_t *__restrict__ present,
+                                                       int64_t n,
+                                                       const double *__restrict__ off_empty,
+                                                       const int32_t *__restrict__ dup_parent,
+                                                       int32_t *__restrict__ out)
+{
+    __shared__ double red[NWAVES];
+    const bool resampled = scalars[SMC_S_RESAMPLED] != 0.0;
+    const int64_t base = (int64_t)blockIdx.x * TILE + ITEMS * threadIdx.x;
+    if (!resampled) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+            if (base + k < n)
+                out[base + k] = (int32_t)(base + k);
+        return;
+    }
+    bool empty[ITEMS];
+    double run = 0.0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        empty[k] = base + k < n && present[base + k] == 0;
+        run += empty[k] ? 1.0 : 0.0;
+    }
+    double total;
+    double r = block_excl_scan<NWAVES>(run, red, &total) + off_empty[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t j = base + k;
+        if (j < n) {
+            if (empty[k]) {
+                out[j] = dup_parent[(int64_t)r];
+                r += 1.0;
+            } else {
+                out[j] = (int32_t)j;
+            }
+        }
+    }
+}
+
+hipError_t launch_copy_from(Ctx &c, int32_t *out)
+{
+    const int64_t n = c.n, nt = c.ntiles;
+    const double *sc = c.buf.scalars;
+    int32_t *present = c.cf_present();
+    int32_t *dup_parent = c.cf_dup();
+    double *cnt_dup = c.cf_tiles(), *cnt_empty = cnt_dup + nt;
+    double *off_dup = cnt_empty + nt, *off_empty = off_dup + (nt + 1);
+    hipLaunchKernelGGL(cf_clear_kernel, dim3((unsigned)ceil_div(n, TPB)), dim3(TPB), 0, c.stream,
+                       sc, present, n);
+    hipLaunchKernelGGL(cf_mark_kernel, dim3((unsigned)nt), dim3(TPB), 0, c.stream, sc,
+                       (const int32_t *)c.buf.ancestors, n, present, cnt_dup);
+    hipLaunchKernelGGL(cf_count_empty_kernel, dim3((unsigned)nt), dim3(TPB), 0, c.stream, sc,
+                       (const int32_t *)present, n, cnt_empty);
+    hipLaunchKernelGGL(cf_scan_kernel, dim3(1), dim3(FIN_TPB), 0, c.stream, sc,
+                       (const double *)cnt_dup, (const double *)cnt_empty, nt, off_dup, off_empty);
+    hipLaunchKernelGGL(cf_dup_kernel, dim3((unsigned)nt), dim3(TPB), 0, c.stream, sc,
+                       (const int32_t *)c.buf.ancestors, n, (const double *)off_dup, dup_parent);
+    hipLaunchKernelGGL(cf_final_kernel, dim3((unsigned)nt), dim3(TPB), 0, c.stream, sc,
+                       (const int32_t *)present, n, (const double *)off_empty,
+                       (const int32_t *)dup_parent, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Raw words of the counter-based streams (for external checks and users).
 // ---------------------------------------------------------------------------
 __global__ void draw_words_kernel(Key key, uint32_t t, uint32_t tag, uint32_t j, uint32_t p,

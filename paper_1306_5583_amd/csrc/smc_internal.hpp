@@ -25,6 +25,8 @@ struct Workspace {
     size_t gtile;      // double[gtiles]: tile sums of the exponentials
     size_t gprefix;    // double[gtiles + 1]
     size_t counters;   // int32[16]: error word, accept counters
+    size_t cf;         // int32[2n]: in-place copy layout (particle marks, duplicate parents)
+    size_t cf_tiles;   // double[2 ntiles + 2 (ntiles + 1)]: its tile counts and offsets
     size_t total;
 };
 
@@ -151,6 +153,9 @@ struct Ctx {
     double *gtile() const { return reinterpret_cast<double *>(ws_base() + ws.gtile); }
     double *gprefix() const { return reinterpret_cast<double *>(ws_base() + ws.gprefix); }
     int32_t *counters() const { return reinterpret_cast<int32_t *>(ws_base() + ws.counters); }
+    int32_t *cf_present() const { return reinterpret_cast<int32_t *>(ws_base() + ws.cf); }
+    int32_t *cf_dup() const { return cf_present() + n; }
+    double *cf_tiles() const { return reinterpret_cast<double *>(ws_base() + ws.cf_tiles); }
 };
 
 enum Counter : int { CNT_ERR = 0, CNT_ACC0 = 1, CNT_ACC1 = 2, CNT_ACC2 = 3 };
@@ -173,6 +178,7 @@ hipError_t launch_resample(Ctx &c, int32_t step, int32_t force);
 hipError_t launch_monitor(Ctx &c, int32_t step, double *out_dev, int rows, bool gather_pending,
                           bool reset_pending);
 hipError_t launch_gather(Ctx &c);
+hipError_t launch_copy_from(Ctx &c, int32_t *out);
 hipError_t launch_draw_words(uint64_t seed, uint32_t t, uint32_t tag, uint32_t j, uint32_t p,
                              int64_t n, uint32_t *out, hipStream_t stream);
 

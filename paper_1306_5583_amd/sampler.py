@@ -88,6 +88,14 @@ class _Base(ProblemBuffers):
     def log_z(self) -> float:
         return self.scalars_host()[L.SMC_S_LOGZ]
 
+    def copy_from(self) -> torch.Tensor:
+        """In-place parent layout (Section 4.1, copy(N, copy_from)) of the
+        last resample: survivors keep their index, the extra copies fill the
+        indices without offspring in ascending order."""
+        out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        L.smc_copy_from(self.ctx, out.data_ptr())
+        return out
+
     def check(self):
         L.smc_check(self.ctx)
 

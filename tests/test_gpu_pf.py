@@ -254,6 +254,39 @@ def test_gather_materialises_state(lib, orc):
     assert np.array_equal(pf.state().cpu().numpy(), before[:, anc])
 
 
+@pytest.mark.parametrize("n,far", [(2500, False), (70001, False), (70001, True),
+                                   (1 << 22, False)])
+def test_copy_from_layout_matches_oracle(lib, orc, n, far):
+    # the in-place parent layout of Section 4.1 from the sorted ancestors,
+    # bit-exact against the oracle's derivation; `far` puts the first
+    # observation far from every particle so that a handful of parents take
+    # almost all slots (long runs of duplicates, mostly empty particles)
+    pkg, L = lib
+    _, y = synth.pf_trajectory(5, 3)
+    if far:
+        y = y.copy()
+        y[0] = (6.0, 6.0)
+    pf = pkg.ParticleFilter(n, y, seed=4, threshold=1.0)
+    pf.init()
+    cf = pf.copy_from().cpu().numpy()
+    anc = pf.ancestors.cpu().numpy()
+    assert pf.scalars_host()[L.SMC_S_RESAMPLED] == 1.0
+    assert np.array_equal(cf, orc.copy_from(anc))
+    if far:
+        assert np.unique(anc).size < n // 10
+    pf.close()
+
+
+def test_copy_from_identity_without_resample(lib):
+    pkg, L = lib
+    _, y = synth.pf_trajectory(5, 3)
+    pf = pkg.ParticleFilter(3000, y, seed=4, threshold=0.0)
+    pf.init()
+    assert pf.scalars_host()[L.SMC_S_RESAMPLED] == 0.0
+    assert np.array_equal(pf.copy_from().cpu().numpy(), np.arange(3000, dtype=np.int32))
+    pf.close()
+
+
 def test_force_resample_and_error_word(lib):
     pkg, L = lib
     _, y = synth.pf_trajectory(5, 3)

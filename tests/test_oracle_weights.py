@@ -157,6 +157,11 @@ def test_copy_from_layout(orc):
     # survivors keep their own slot; the multiset of parents is unchanged
     assert np.all(cf[R > 0] == np.nonzero(R > 0)[0])
     assert np.array_equal(np.sort(cf), anc)
+    # the empty slots, in ascending order, take the extra copies in
+    # ascending (parent, copy) order: the sorted ancestors minus the first
+    # copy of each parent
+    extras = anc[1:][anc[1:] == anc[:-1]]
+    assert np.array_equal(cf[R == 0], extras)
 
 
 def test_weighted_mean(orc):
