@@ -486,7 +486,16 @@ def _study_batch(y, K, n, T, method, seeds, seed0):
     br = pkg.BatchRunner(specs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    br.run(T, graph=True)
+    br.init()
+    br.capture()
+    for k in range(T):
+        br.replay()
+        if (k + 1) % 200 == 0 and k + 1 < T:
+            # a progress line per 200 steps (long configurations run for minutes)
+            br.stream.synchronize()
+            print("#   %s N=%d T=%d: step %d, %.1f s" % (method, n, T, k + 1,
+                                                        time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     br.check()
