@@ -62,7 +62,7 @@ typedef enum {
     SMC_ERR_BAD_STATE = 2,   /* call out of order (e.g. resample before init) */
     SMC_ERR_DEVICE = 3,      /* HIP runtime error or no usable gfx950 device */
     SMC_ERR_NUMERIC = 4,     /* device error word set (see SMC_DEVERR_*) */
-    SMC_ERR_UNSUPPORTED = 5  /* valid request this build does not provide */
+    SMC_ERR_UNSUPPORTED = 5  /* valid request the library does not provide */
 } smc_status;
 
 typedef enum { SMC_MODEL_CV_TRACK = 1, SMC_MODEL_GMM_TEMPERED = 2 } smc_model;
