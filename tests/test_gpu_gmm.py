@@ -176,16 +176,21 @@ def test_lockstep_two_sweeps(lib, orc):
     _lockstep_gmm(lib, orc, 2500, 4, 120, 6, "rw", sweeps=2)
 
 
-def test_end_to_end_small(lib, orc):
+@pytest.mark.parametrize("move", ["rw", "mala"])
+def test_end_to_end_small(lib, orc, move):
+    # two independent whole runs (direct and path-sampling log Z, decisions,
+    # accept counts), random walk and MALA
     pkg, L = lib
-    K, n, nd, T = 4, 4096, 100, 20
+    K, n, nd, T = (4, 4096, 100, 20) if move == "rw" else (3, 2048, 80, 12)
     y = synth.gmm_data_four_components(nd, 8)
     alphas = synth.prior_tempering(T, 4.0)
-    s = pkg.GmmSampler(n, y, K, T, seed=5)
+    s = pkg.GmmSampler(n, y, K, T, seed=5, move=move)
     logz_g = s.run(alphas)
     hist = s.history_host()
-    scales = np.array([pkg.rw_scales(a) for a in alphas])
-    logz_o, hist_o, pop_o, lwf_o = orc.gmm_run(orc.gmm_cfg(n, 5, K), y, alphas, scales)
+    f = pkg.rw_scales if move == "rw" else pkg.mala_scales
+    scales = np.array([f(a) for a in alphas])
+    logz_o, hist_o, pop_o, lwf_o = orc.gmm_run(orc.gmm_cfg(n, 5, K, move=move), y, alphas,
+                                               scales)
     assert abs(logz_g - logz_o) <= 1e-9 * max(1.0, np.abs(hist_o[:, 2]).sum()) + 1e-9
     assert np.array_equal(hist[1:, L.SMC_H_FLAG], hist_o[1:, 1])
     acc_g = hist[1:, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3]
