@@ -140,7 +140,26 @@ __device__ void mon_combine(const double *__restrict__ mon, int64_t ntiles, cons
 {
     constexpr int NW = NTHR / WAVE;
     const int tid = threadIdx.x, w = wave_id();
-    for (int r0 = 0; r0 <= d.rows; r0 += 2) {
+    if (ntiles <= NTHR) {
+        // one tile per thread: up to 16 rows' loads in flight per round
+        // (the same sums in the same order as below)
+        constexpr int RG = 16;
+        for (int r0 = 0; r0 <= d.rows; r0 += RG) {
+            double x[RG];
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+                x[g] = (r0 + g <= d.rows && tid < ntiles) ? mon[(int64_t)(r0 + g) * ntiles + tid]
+                                                          : 0.0;
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+                if (r0 + g <= d.rows) {
+                    const double v = wave_sum(x[g]);
+                    if (lane_id() == 0)
+                        red[(r0 + g) * NW + w] = v;
+                }
+        }
+    }
+    for (int r0 = 0; ntiles > NTHR && r0 <= d.rows; r0 += 2) {
         const bool two = r0 + 1 <= d.rows;
         const double *m0 = mon + (int64_t)r0 * ntiles;
         const double *m1 = two ? m0 + ntiles : m0;
