@@ -71,6 +71,8 @@ def _parse():
     ap.add_argument("--study-methods", default="mala,rw,rw:0.05")
     ap.add_argument("--study-tol", type=float, default=0.05)
     ap.add_argument("--study-seeds", type=int, default=16)
+    ap.add_argument("--study-seed-base", type=int, default=100000,
+                    help="study: first sampler seed of a configuration is base + 1000 T")
     ap.add_argument("--study-ref-method", default=None)
     ap.add_argument("--study-ref-log-z", type=float, default=None)
     ap.add_argument("--study-ref-seeds", type=int, default=4)
@@ -534,12 +536,13 @@ def bench_study(args):
     for method in methods:
         for T in Ts:
             for n in Ns:
-                z, wall = _study_batch(y, K, n, T, method, args.study_seeds, 100000 + 1000 * T)
+                z, wall = _study_batch(y, K, n, T, method, args.study_seeds,
+                                       args.study_seed_base + 1000 * T)
                 rmse = float(np.sqrt(np.mean((z - zstar) ** 2)))
                 cost = wall / args.study_seeds
                 grid.append({"method": method, "T": T, "n": n, "rmse": rmse,
                              "bias": float(z.mean() - zstar), "sd": float(z.std(ddof=1)),
-                             "gpu_s": cost})
+                             "gpu_s": cost, "log_z": z.tolist()})
                 print("# %s T=%d N=%d rmse %.4f bias %+.4f sd %.4f gpu_s %.4f" % (
                     method, T, n, rmse, z.mean() - zstar, z.std(ddof=1), cost),
                     file=sys.stderr, flush=True)
