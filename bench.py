@@ -202,6 +202,27 @@ def cpu_baseline_pf(args):
                       % (n, T, T - 1, args.scheme, wall)}
 
 
+def cpu_baseline_gmm(workload, K, nd, y, move):
+    """The oracle's whole sampler (Algorithm 'gmm', same data, schedule and
+    move) on a bounded sample: fewer particles and the first steps of the
+    schedule (the work per step does not depend on alpha)."""
+    import oracle
+    import synth
+    from paper_1306_5583_amd import mala_scales, rw_scales
+    n, Ts, T = (1 << 12, 25, 100) if workload == "gmm-c2" else (1 << 9, 10, 200)
+    alphas = synth.prior_tempering(T, 4.0)[:Ts + 1]
+    f = rw_scales if move == "rw" else mala_scales
+    scales = np.array([f(a) for a in alphas])
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.gmm_run(oracle.gmm_cfg(n, 1, K, move=move), y, alphas, scales)
+    wall = time.perf_counter() - t0
+    return {"value": n * Ts / wall, "unit": METRIC, "cores": 1, "kind": "oracle",
+            "sample": "mixture sampler K=%d, n=%d data, N=%d, the first %d of %d steps "
+                      "(init inside the wall), %s moves, single-threaded C oracle; wall %.2f s"
+                      % (K, nd, n, Ts, T, move, wall)}
+
+
 def pf_traffic():
     """HBM bytes per move launch from the committed FETCH_SIZE / WRITE_SIZE
     summary, scaled by the copy-kernel calibration; None when the summary
@@ -366,6 +387,8 @@ def bench_gmm(args):
         "resamples": int(hist[1:, L.SMC_H_FLAG].sum()),
     }
     s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_gmm(args.workload, K, nd, y, move)
     return out
 
 
