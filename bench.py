@@ -351,16 +351,17 @@ def bench_gmm(args):
     warm.close()
     s = GmmSampler(n, y, K, T, seed=1, move=move)
     blocks = 3 if K > 1 else 2
-    L.smc_profile_start(s.ctx, T * blocks)
+    # one Metropolis launch per step covers its `blocks` likelihood passes
+    L.smc_profile_start(s.ctx, T)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     logz = s.run(alphas)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    blk_ms = L.smc_profile_read(s.ctx, T * blocks)
+    blk_ms = L.smc_profile_read(s.ctx, T)
     s.check()
     hist = s.history_host()
-    terms_per_launch = n * nd * K
+    terms_per_launch = n * nd * K * blocks
     avg_ms = float(np.mean(blk_ms))
     v = read_profile_values("gmm_block_%s_fp64.txt" % args.workload.split("-")[1])
     flops = None
@@ -377,8 +378,9 @@ def bench_gmm(args):
                    "K": K, "n_data": nd, "n": n, "T": T, "move": move},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS if achieved else None,
-                     "traffic": None, "kernel": "gmm_block_kernel (Metropolis block: proposal, "
-                     "mixture likelihood%s, accept)" % (" and gradient" if move == "mala" else ""),
+                     "traffic": None, "kernel": "gmm_step_kernel (the step's Metropolis blocks: "
+                     "proposal, mixture likelihood%s, accept)" % (" and gradient" if move == "mala"
+                                                                 else ""),
                      "avg_launch_ms": avg_ms, "terms_per_launch": terms_per_launch},
         "terms_per_s": terms_per_launch / (avg_ms * 1e-3),
         "log_z": logz,

@@ -303,7 +303,8 @@ smc_status smc_draw_words(uint64_t seed, uint32_t step, uint32_t tag, uint32_t c
 /* Timing of the sweep's dominant kernel by events carried in the kernel's
  * own dispatch, so the stream receives no extra packets: the next `count`
  * launches of the tracking filter's move kernel, or of the mixture
- * sampler's Metropolis-block kernel (one per block), of this context are
+ * sampler's Metropolis kernel (one launch per smc_move: all its blocks and
+ * sweeps), of this context are
  * timed (count = 0 disarms).  smc_profile_read waits for them and writes
  * up to `capacity` durations in milliseconds, in launch order; *written
  * receives how many.  Host-side bookkeeping only; events are owned by the

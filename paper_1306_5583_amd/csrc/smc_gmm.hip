@@ -163,29 +163,20 @@ hipError_t launch_gmm_reweight(Ctx &c, double dalpha, bool reset_check)
 
 hipError_t launch_gmm_move(Ctx &c, int32_t step, const smc_move_args &a, bool gather_check)
 {
+    // every block of every sweep in one launch (gmm_step_kernel)
     const int W = gmm_waves(c.n, c.cfg.n_data);
     const int sweeps = a.sweeps > 0 ? a.sweeps : (c.cfg.sweeps > 0 ? c.cfg.sweeps : 1);
-    bool gather = gather_check;
-    for (int s = 0; s < sweeps; ++s) {
-        for (int b = 0; b < 3; ++b) {
-            if (b == 2 && c.cfg.K == 1)
-                continue;
-#define CALL_BLOCK(k) GmmK<k>::block(c, W, step, b, s, a.alpha, a.scale[b], gather)
-            hipError_t e;
-            {
-                auto f = [&]() -> hipError_t { SMC_K_SWITCH(c.cfg.K, CALL_BLOCK) };
-                e = f();
-            }
-#undef CALL_BLOCK
-            if (e != hipSuccess)
-                return e;
-            if (gather) {
-                c.cur ^= 1;
-                gather = false;
-            }
-        }
+    const double scale[3] = {a.scale[0], a.scale[1], a.scale[2]};
+#define CALL_STEP(k) GmmK<k>::step(c, W, step, sweeps, a.alpha, scale, gather_check)
+    hipError_t e;
+    {
+        auto f = [&]() -> hipError_t { SMC_K_SWITCH(c.cfg.K, CALL_STEP) };
+        e = f();
     }
-    return hipSuccess;
+#undef CALL_STEP
+    if (e == hipSuccess && gather_check)
+        c.cur ^= 1;
+    return e;
 }
 
 hipError_t launch_gmm_loglik_grad(const double *mu, const double *eta, const double *z,

@@ -586,13 +586,26 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
                   (double)__popcll(bal));
 }
 
+// All Metropolis blocks of a step (every sweep) in one launch: the tile's
+// workgroup runs the blocks one after the other, each reading back the state
+// the previous block's wave 0 wrote for the same particles (visible to the
+// workgroup after the barrier).  The first block reads `src` (through the
+// ancestors when the step resampled and `full` is set) and writes `dst`;
+// later blocks update `dst` in place.
 template <int K, bool MALA>
-__global__ __launch_bounds__(GMM_MAXW *WAVE) void gmm_block_kernel(
+__global__ __launch_bounds__(GMM_MAXW *WAVE) void gmm_step_kernel(
     Prob P, const double *__restrict__ src, double *__restrict__ dst, int full, int W, uint32_t t,
-    int block, int sweep, double alpha, double scale, int32_t step)
+    int sweeps, double alpha, double s0, double s1, double s2, int32_t step)
 {
-    gmm_block_tile<K, MALA>(P, src, dst, full, W, blockIdx.x, t, block, sweep, alpha, scale,
-                            step);
+    const int nb = K == 1 ? 2 : 3;
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int b = 0; b < nb; ++b) {
+            const bool first = sw == 0 && b == 0;
+            if (!first)
+                __syncthreads();
+            gmm_block_tile<K, MALA>(P, first ? src : dst, dst, first ? full : 0, W, blockIdx.x,
+                                    t, b, sw, alpha, b == 0 ? s0 : (b == 1 ? s1 : s2), step);
+        }
 }
 
 // Batched: the step, alpha_t and the block scale come from the device (the
@@ -667,8 +680,8 @@ int gmm_waves(int64_t n, int64_t nd);
 template <int K>
 struct GmmK {
     static hipError_t init(Ctx &c, int W);
-    static hipError_t block(Ctx &c, int W, int32_t step, int block, int sweep, double alpha,
-                            double scale, bool gather_check);
+    static hipError_t step(Ctx &c, int W, int32_t step, int sweeps, double alpha,
+                           const double (&scale)[3], bool gather_check);
     static hipError_t loglik(const double *mu, const double *eta, const double *z, int64_t n,
                              const double *y, int64_t nd, double *ll, double *grad, hipStream_t s);
     static hipError_t init_batch(const Prob *probs, const int2 *map, int64_t tiles, int W,
@@ -693,36 +706,33 @@ hipError_t GmmK<K>::init(Ctx &c, int W)
 }
 
 template <int K>
-hipError_t GmmK<K>::block(Ctx &c, int W, int32_t step, int block, int sweep, double alpha,
-                                 double scale, bool gather_check)
+hipError_t GmmK<K>::step(Ctx &c, int W, int32_t step, int sweeps, double alpha,
+                         const double (&scale)[3], bool gather_check)
 {
     const dim3 grid((unsigned)ceil_div(c.n, WAVE)), blk((unsigned)(W * WAVE));
-    const Key key = make_key(c.cfg.seed);
     const double *src = (const double *)c.state_ptr();
     double *dst = gather_check ? (double *)c.other_ptr() : (double *)c.state_ptr();
     const Prob P = make_prob(c);
-    (void)key;
     hipEvent_t e0, e1;
     const bool timed = c.prof_take(&e0, &e1);
+#define SMC_STEP_ARGS                                                                             \
+    P, src, dst, (int)gather_check, W, (uint32_t)step, sweeps, alpha, scale[0], scale[1],         \
+        scale[2], step
     if (c.cfg.move_kind == SMC_MOVE_MALA) {
         if (timed)
-            hipExtLaunchKernelGGL((gmm_block_kernel<K, true>), grid, blk, 0, c.stream, e0, e1, 0,
-                                  P, src, dst, (int)gather_check, W, (uint32_t)step, block, sweep,
-                                  alpha, scale, step);
+            hipExtLaunchKernelGGL((gmm_step_kernel<K, true>), grid, blk, 0, c.stream, e0, e1, 0,
+                                  SMC_STEP_ARGS);
         else
-            hipLaunchKernelGGL((gmm_block_kernel<K, true>), grid, blk, 0, c.stream, P, src, dst,
-                               (int)gather_check, W, (uint32_t)step, block, sweep, alpha, scale,
-                               step);
+            hipLaunchKernelGGL((gmm_step_kernel<K, true>), grid, blk, 0, c.stream, SMC_STEP_ARGS);
     } else {
         if (timed)
-            hipExtLaunchKernelGGL((gmm_block_kernel<K, false>), grid, blk, 0, c.stream, e0, e1, 0,
-                                  P, src, dst, (int)gather_check, W, (uint32_t)step, block, sweep,
-                                  alpha, scale, step);
+            hipExtLaunchKernelGGL((gmm_step_kernel<K, false>), grid, blk, 0, c.stream, e0, e1, 0,
+                                  SMC_STEP_ARGS);
         else
-            hipLaunchKernelGGL((gmm_block_kernel<K, false>), grid, blk, 0, c.stream, P, src, dst,
-                               (int)gather_check, W, (uint32_t)step, block, sweep, alpha, scale,
-                               step);
+            hipLaunchKernelGGL((gmm_step_kernel<K, false>), grid, blk, 0, c.stream,
+                               SMC_STEP_ARGS);
     }
+#undef SMC_STEP_ARGS
     return hipGetLastError();
 }
 
