@@ -326,13 +326,20 @@ def bench_pf_c0(args):
     wall = time.perf_counter() - t0
     logz_graph = br.log_z(0)
     br.close()
+    # the value is the faster of the two ways of issuing the same steps (the
+    # eager launches here: a graph replay costs more than three launches at
+    # this size); both are reported
+    eager_s = eager_ms * 1e-3 * steps
+    best_wall = min(wall, eager_s)
     return {
-        "metric": METRIC, "value": 1000 * steps / wall, "unit": METRIC, "n_gpus": 1,
-        "steps": steps, "warmup": 1, "ms_per_step": 1e3 * wall / steps,
+        "metric": METRIC, "value": 1000 * steps / best_wall, "unit": METRIC, "n_gpus": 1,
+        "steps": steps, "warmup": 1, "ms_per_step": 1e3 * best_wall / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "tracking particle filter, N=1000, T=100, systematic at "
-                               "ESS<N/2, graph replay per step", "n": 1000, "T": 100},
+                               "ESS<N/2, %s" % ("eager launches" if eager_s <= wall
+                                                else "graph replay per step"),
+                   "n": 1000, "T": 100},
         "latency_ms": {"graph_p50": float(np.percentile(lat, 50)),
                        "graph_p99": float(np.percentile(lat, 99)),
                        "eager_mean": eager_ms},
