@@ -318,75 +318,14 @@ int orc_ancestors(const double *lw, int64_t n, const double *u, int32_t *anc,
     return 0;
 }
 
-/*
- * Systematic replication numbers (Section 2.1: integers R_j >= 0 summing to
- * N, particle j copied R_j times).  With S_j and S as in orc_ancestors,
- * particle j receives the slots [c(S_{j-1}), c(S_j)) (c(S_{-1}) = 0), where
- * c(x) = min(N, max(0, ceil(fma(x, N/S, -U)))) is the number of ordered
- * uniforms (i + U)/N lying below x/S, written in closed form; so
- * R_j = c(S_j) - c(S_{j-1}).  Slots from c(S_{N-1}) to N (left when U = 1
- * or by rounding) go to the last particle of positive weight.  Returns 0,
- * or -1 when all weights are zero or not finite.
- */
-static int64_t sys_count(double x, double r, double U, int64_t n)
-{
-    const double c = ceil(fma(x, r, -U));
-    if (!(c > 0.0))
-        return 0;
-    return c >= (double)n ? n : (int64_t)c;
-}
-
-int orc_systematic_ancestors(const double *lw, int64_t n, double U, int32_t *anc,
-                             double *S_out)
-{
-    double m = orc_max(lw, n);
-    if (!(m > -INFINITY) || !isfinite(m))
-        return -1;
-    double *S = (double *)malloc(sizeof(double) * (size_t)n);
-    ksum acc = {0.0, 0.0};
-    for (int64_t j = 0; j < n; ++j) {
-        ks_add(&acc, exp(lw[j] - m));
-        S[j] = ks_val(&acc);
-    }
-    double tot = S[n - 1];
-    if (!(tot > 0.0) || !isfinite(tot)) {
-        free(S);
-        return -1;
-    }
-    const double r = (double)n / tot;
-    int64_t last = 0, start = 0;
-    for (int64_t j = 0; j < n; ++j) {
-        if (S[j] > (j ? S[j - 1] : 0.0))
-            last = j;
-        const int64_t end = sys_count(S[j], r, U, n);
-        for (int64_t i = start; i < end; ++i)
-            anc[i] = (int32_t)j;
-        if (end > start)
-            start = end;
-    }
-    for (int64_t i = start; i < n; ++i)
-        anc[i] = (int32_t)last;
-    if (S_out)
-        memcpy(S_out, S, sizeof(double) * (size_t)n);
-    free(S);
-    return 0;
-}
-
-/* Full resampling step: ordered uniforms then ancestors (systematic: the
- * closed-form replication numbers above; u is still reported). */
+/* Full resampling step (every scheme): its ordered uniforms, then the
+ * inverse of the cumulative weights at each of them. */
 int orc_resample(int scheme, uint64_t seed, uint32_t t, uint32_t p, const double *lw,
                  int64_t n, int32_t *anc, double *S_out, double *u_out)
 {
     double *u = (double *)malloc(sizeof(double) * (size_t)n);
     orc_resample_uniforms(scheme, seed, t, p, n, u);
-    int rc;
-    if (scheme == ORC_RS_SYSTEMATIC) {
-        uint32_t w[4];
-        draw(seed, 0, t, ORC_TAG_RESAMPLE, 0, p, w);
-        rc = orc_systematic_ancestors(lw, n, orc_u53(w[0], w[1]), anc, S_out);
-    } else {
-        rc = orc_ancestors(lw, n, u, anc, S_out);
-    }
+    int rc = orc_ancestors(lw, n, u, anc, S_out);
     if (u_out)
         memcpy(u_out, u, sizeof(double) * (size_t)n);
     free(u);

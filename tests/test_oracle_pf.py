@@ -59,6 +59,52 @@ def test_move_one_step_kalman_moments(orc):
     assert np.all(np.abs(x1.std(axis=1) / sd - 1) < 0.02)
 
 
+def test_move_one_step_moments_fp32(orc):
+    # the FP32-state branch: float normals, float transition from a fixed
+    # point.  Mean A x with the old velocity (a dropped dt moves the position
+    # mean by 0.9 x_vel), position sd 0.02 alone (the new velocity in the
+    # position update would make it sqrt(0.02^2 + (0.1 * 0.5)^2) = 0.054),
+    # independent coordinates, float-representable results.
+    n = 200_000
+    cfg = orc.pf_cfg(n, 9, fp32_state=True)
+    x0 = np.tile(np.array([[1.0], [-2.0], [3.0], [0.5]]), (1, n))
+    y = np.array([1.25, -1.9])
+    x1, lw1 = orc.pf_move(cfg, 4, y, x0, np.zeros(n), True)
+    assert np.array_equal(x1.astype(np.float32).astype(np.float64), x1)
+    mean = np.array([1.0 + 0.1 * 3.0, -2.0 + 0.1 * 0.5, 3.0, 0.5])
+    sd = np.array([0.02, 0.02, 0.5, 0.5])
+    # float rounding of the mean itself: a few ulp of |x| ~ 1e-7, far inside
+    assert np.all(np.abs(x1.mean(axis=1) - mean) < 5 * sd / math.sqrt(n) + 1e-6)
+    assert np.all(np.abs(x1.std(axis=1) / sd - 1) < 0.02)
+    c = np.corrcoef(x1)
+    assert np.all(np.abs(c[np.triu_indices(4, 1)]) < 5 / math.sqrt(n))
+    # the increment is the FP64 observation density at the new float position
+    for i in range(0, n, 20_000):
+        ref = (stats.t.logpdf(y[0], df=10, loc=x1[0, i], scale=0.1) +
+               stats.t.logpdf(y[1], df=10, loc=x1[1, i], scale=0.1))
+        assert lw1[i] == pytest.approx(ref, abs=1e-11)
+    # the float noise does not reuse the FP64 stream's values
+    x64, _ = orc.pf_move(orc.pf_cfg(n, 9), 4, y, x0, np.zeros(n), True)
+    assert not np.allclose(x1[2], x64[2], rtol=0, atol=1e-3)
+
+
+def test_init_moments_fp32(orc):
+    cfg = orc.pf_cfg(200_000, 5, init_sd=(2.0, 2.0, 1.0, 1.0), fp32_state=True)
+    y0 = np.array([0.3, -0.2])
+    x, lw = orc.pf_init(cfg, y0)
+    n = cfg.n
+    assert np.array_equal(x.astype(np.float32).astype(np.float64), x)
+    for k, sd in enumerate([2.0, 2.0, 1.0, 1.0]):
+        assert abs(x[k].mean()) < 5 * sd / math.sqrt(n)
+        assert abs(x[k].var() / sd ** 2 - 1) < 5 * math.sqrt(2 / n)
+    c = np.corrcoef(x)
+    assert np.all(np.abs(c[np.triu_indices(4, 1)]) < 5 / math.sqrt(n))
+    for i in range(0, n, 40_000):
+        ref = (stats.t.logpdf(y0[0], df=10, loc=x[0, i], scale=0.1) +
+               stats.t.logpdf(y0[1], df=10, loc=x[1, i], scale=0.1))
+        assert lw[i] == pytest.approx(ref, abs=1e-11)
+
+
 def test_lw_reset_and_accumulate(orc):
     rng = np.random.default_rng(0)
     n = 100
@@ -81,16 +127,21 @@ def _kf_case(T, data_seed):
     return y, ll, means
 
 
-@pytest.mark.parametrize("scheme", ["systematic", "multinomial"])
-def test_filter_log_evidence_matches_kalman(orc, scheme):
+@pytest.mark.parametrize("scheme,fp32", [("systematic", False), ("multinomial", False),
+                                         ("systematic", True), ("multinomial", True)])
+def test_filter_log_evidence_matches_kalman(orc, scheme, fp32):
     # PF log Z is unbiased for Z; over several seeds it sits within a few
-    # standard errors of the exact Kalman-filter log p(y_0..T-1)
+    # standard errors of the exact Kalman-filter log p(y_0..T-1).  The
+    # FP32-state variant (float state, draws and transition; FP64 weights)
+    # must reach the same evidence: its rounding (~1e-7 of the state) is far
+    # below the Monte Carlo error, while a dropped term of its transition
+    # moves log Z by many standard errors.
     T = 40
     y, ll_kf, means_kf = _kf_case(T, 4242)
     vals = []
     est_means = []
     for seed in range(1, 9):
-        cfg = orc.pf_cfg(1 << 14, seed, obs_nu=math.inf, scheme=scheme)
+        cfg = orc.pf_cfg(1 << 14, seed, obs_nu=math.inf, scheme=scheme, fp32_state=fp32)
         logz, hist, _, _ = orc.pf_run(cfg, y)
         vals.append(logz)
         est_means.append(hist[:, 5:9])

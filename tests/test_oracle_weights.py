@@ -190,10 +190,14 @@ def test_ties_go_right_and_clamp(orc):
 
 
 def test_systematic_counts_closed_form_exact(orc):
-    # R_j = ceil(N S_j / S - U) - ceil(N S_{j-1} / S - U) in exact rational
-    # arithmetic on the oracle's own cumulative weights (slots past the last
-    # count go to the last positive weight); only counts whose argument lies
-    # within 1e-12 of an integer may round the other way
+    # The oracle takes a_i = min{j : S_j > u_i S} at u_i = (i + U)/N.  In
+    # exact arithmetic that gives particle j the replication number
+    # R_j = c(S_j) - c(S_{j-1}) with c(x) = #{i : (i + U)/N < x/S} =
+    # ceil(N x / S - U) clamped to [0, N] (Section 2.1's counts, a different
+    # route to the same integers), checked here in rational arithmetic on
+    # the oracle's own cumulative weights (slots past the last count go to
+    # the last positive weight); only counts whose argument lies within
+    # 1e-12 of an integer may round the other way
     from fractions import Fraction
     rng = np.random.default_rng(21)
     for trial in range(12):
