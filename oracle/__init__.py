@@ -35,7 +35,7 @@ def build(force: bool = False) -> str:
             return _LIB_PATH
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"]
+           "-fopenmp", "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -76,6 +76,8 @@ class GmmCfg(ctypes.Structure):
 
 def _declare(L):
     sig = {
+        "orc_set_threads": (None, [_i32]),
+        "orc_max_threads": (_i32, []),
         "orc_philox": (None, [_up, _up, _up]),
         "orc_draw_words": (None, [_u64, _u32, _u32, _u32, _u32, _u32, _up]),
         "orc_u53": (_d, [_u32, _u32]),
@@ -108,6 +110,11 @@ def _declare(L):
                                  _dp, _dp, _dp, _dp, _ip]),
         "orc_gmm_block_trace": (_i32, [ctypes.POINTER(GmmCfg), _u32, _i32, _i32, _d, _d, _dp,
                                        _i64, _dp, _dp, _dp, _dp, _ip, _dp, _dp]),
+        "orc_gmm_block_trace_ids": (_i32, [ctypes.POINTER(GmmCfg), _u32, _i32, _i32, _d, _d,
+                                           _dp, _i64, ctypes.POINTER(_i64), _i64, _dp, _dp, _dp,
+                                           _dp, _ip, _dp, _dp]),
+        "orc_gmm_init_ids": (_i32, [ctypes.POINTER(GmmCfg), _dp, _i64, ctypes.POINTER(_i64), _i64,
+                                    _dp, _dp, _dp]),
         "orc_gmm_run": (_d, [ctypes.POINTER(GmmCfg), _dp, _i64, _i32, _dp, _dp, _dp, _dp, _dp]),
         "orc_path_sampling": (_d, [_dp, _dp, _i64]),
     }
@@ -117,6 +124,16 @@ def _declare(L):
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+
+
+def set_threads(n: int) -> None:
+    """Threads for the oracle's independent per-particle loops (the sums stay
+    sequential in index order, so results do not depend on the count)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _d_ptr(a):
@@ -404,18 +421,62 @@ def gmm_block_trace(cfg, t, block, sweep, alpha, scale, y, pop, ll, lp, grad=Non
     return pop, ll, lp, grad, acc, logr, logu
 
 
+def _ids(ids):
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    return ids, ids.ctypes.data_as(ctypes.POINTER(_i64))
+
+
+def gmm_init_ids(cfg, y, ids):
+    """gmm_init for the particles `ids` only: (pop[D][m], ll[m], lp[m]),
+    column q being particle ids[q]."""
+    y = _f64(y)
+    ids, pids = _ids(ids)
+    m = ids.size
+    D = 3 * cfg.K - 1
+    pop = np.zeros((D, m))
+    ll = np.zeros(m)
+    lp = np.zeros(m)
+    lib().orc_gmm_init_ids(ctypes.byref(cfg), _d_ptr(y), y.size, pids, m, _d_ptr(pop),
+                           _d_ptr(ll), _d_ptr(lp))
+    return pop, ll, lp
+
+
+def gmm_block_trace_ids(cfg, t, block, sweep, alpha, scale, y, ids, pop, ll, lp, grad=None):
+    """gmm_block_trace for the particles `ids` only (columns of pop, ll, lp,
+    grad in the order of ids): the Metropolis blocks act on each particle
+    independently, so a sample of columns can be checked on its own."""
+    y = _f64(y)
+    ids, pids = _ids(ids)
+    m = ids.size
+    pop = _f64(pop).copy()
+    ll = _f64(ll).copy()
+    lp = _f64(lp).copy()
+    grad = None if grad is None else _f64(grad).copy()
+    acc = np.zeros(m, dtype=np.int32)
+    logr = np.zeros(m)
+    logu = np.zeros(m)
+    lib().orc_gmm_block_trace_ids(ctypes.byref(cfg), t, block, sweep, alpha, scale, _d_ptr(y),
+                                  y.size, pids, m, _d_ptr(pop), _d_ptr(ll), _d_ptr(lp),
+                                  None if grad is None else _d_ptr(grad), _i_ptr(acc),
+                                  _d_ptr(logr), _d_ptr(logu))
+    return pop, ll, lp, grad, acc, logr, logu
+
+
 def gmm_run(cfg, y, alpha, scales):
-    """Whole sampler (Algorithm "gmm"); returns (logZ, hist[T+1][10],
+    """Whole sampler (Algorithm "gmm"); returns (logZ, hist[T+1][13],
     pop_final, lw_final).
 
     hist columns: ESS, resampled, dlogZ, logZ (Eq. smc-ds), L,
-    accepts(mu, eta, z), U_t (Eq. path_import) and the running path-sampling
-    estimate (Eq. path_est)."""
+    accepts(mu, eta, z), U_t (Eq. path_import), the running path-sampling
+    estimate (Eq. path_est), and the step's decision margins: Metropolis
+    (|log r - log u| over the size of log r's terms), resampling decision
+    (|ESS - tau N| / tau N) and ancestors (distance of u_i S from the nearer
+    bracketing cumulative weight, over S)."""
     y = _f64(y)
     alpha = _f64(alpha)
     T = alpha.size - 1
     scales = _f64(scales).reshape(T + 1, 3)
-    hist = np.zeros((T + 1, 10))
+    hist = np.zeros((T + 1, 13))
     D = 3 * cfg.K - 1
     pop = np.zeros((D, cfg.n))
     lwf = np.zeros(cfg.n)

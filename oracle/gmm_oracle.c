@@ -15,6 +15,7 @@
  * structure-of-arrays [3K-1][n].
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -35,7 +36,7 @@ typedef struct {
 
 static const double LOG_2PI = 1.8378770664093454835606594728112;
 /* columns of the per-step record of orc_gmm_run */
-#define ORC_GMM_HIST_COLS 10
+#define ORC_GMM_HIST_COLS 13
 
 /* log omega_j for j = 0..K-1 from the K-1 logits (reference component K). */
 static void log_weights(const double *z, int K, double *logw)
@@ -181,31 +182,33 @@ static void put_phi(double *pop, int64_t n, int D, int64_t i, const double *phi)
  * [3K-1][n], the log-likelihood ll[n] and the log prior lp[n].  Returns the
  * number of failed gamma draws.
  */
-int32_t orc_gmm_init(const orc_gmm_cfg *c, const double *y, int64_t nd, double *pop,
-                     double *ll, double *lp)
+static int32_t gmm_init_impl(const orc_gmm_cfg *c, const double *y, int64_t nd, double *pop,
+                             double *ll, double *lp, const int64_t *ids, int64_t m_ids)
 {
     int K = c->K, D = 3 * K - 1;
-    int64_t n = c->n;
+    int64_t n = ids ? m_ids : c->n;
     int32_t fails = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : fails)
     for (int64_t i = 0; i < n; ++i) {
         double phi[3 * 64], H[64];
+        const uint32_t pid = (uint32_t)(ids ? ids[i] : i);
         for (int j = 0; j < K; j += 2) {
             double z[2];
-            orc_normal2(c->seed, (uint32_t)i, 0, ORC_TAG_INIT, (uint32_t)(j / 2), c->problem, z);
+            orc_normal2(c->seed, pid, 0, ORC_TAG_INIT, (uint32_t)(j / 2), c->problem, z);
             phi[j] = c->mu_mean + c->mu_sd * z[0];
             if (j + 1 < K)
                 phi[j + 1] = c->mu_mean + c->mu_sd * z[1];
         }
         for (int j = 0; j < K; ++j) {
             int f = 0;
-            double G = orc_gamma(c->seed, (uint32_t)i, 0, ORC_TAG_INIT, (uint32_t)(64 + 64 * j),
+            double G = orc_gamma(c->seed, pid, 0, ORC_TAG_INIT, (uint32_t)(64 + 64 * j),
                                  c->problem, c->gamma_shape, &f);
             fails += f;
             phi[K + j] = log(G / c->gamma_rate);
         }
         for (int j = 0; j < K; ++j) {
             int f = 0;
-            H[j] = orc_gamma(c->seed, (uint32_t)i, 0, ORC_TAG_INIT,
+            H[j] = orc_gamma(c->seed, pid, 0, ORC_TAG_INIT,
                              (uint32_t)(64 + 64 * 16 + 64 * j), c->problem, c->dir_rho, &f);
             fails += f;
         }
@@ -216,6 +219,19 @@ int32_t orc_gmm_init(const orc_gmm_cfg *c, const double *y, int64_t nd, double *
         lp[i] = orc_gmm_logprior(c, phi);
     }
     return fails;
+}
+
+int32_t orc_gmm_init(const orc_gmm_cfg *c, const double *y, int64_t nd, double *pop,
+                     double *ll, double *lp)
+{
+    return gmm_init_impl(c, y, nd, pop, ll, lp, NULL, 0);
+}
+
+/* Prior draws of the particles ids[0..m-1] only (column q = particle ids[q]). */
+int32_t orc_gmm_init_ids(const orc_gmm_cfg *c, const double *y, int64_t nd, const int64_t *ids,
+                         int64_t m, double *pop, double *ll, double *lp)
+{
+    return gmm_init_impl(c, y, nd, pop, ll, lp, ids, m);
 }
 
 /*
@@ -252,10 +268,13 @@ static double tempered(double lp, double ll, double alpha)
 static int32_t gmm_block_impl(const orc_gmm_cfg *c, uint32_t t, int32_t block, int32_t sweep,
                               double alpha, double scale, const double *y, int64_t nd,
                               double *pop, double *ll, double *lp, double *grad,
-                              int32_t *accepted, double *logr_out, double *logu_out)
+                              int32_t *accepted, double *logr_out, double *logu_out,
+                              double *scale_out, const int64_t *ids, int64_t m_ids)
 {
     int K = c->K, D = 3 * K - 1;
-    int64_t n = c->n;
+    /* with ids, the arrays hold m_ids particles and column q is particle
+       ids[q] (its random numbers are that particle's) */
+    int64_t n = ids ? m_ids : c->n;
     int off = block * K;
     int dim = block == 2 ? K - 1 : K;
     uint32_t tag = (uint32_t)(ORC_TAG_MH_MU + block);
@@ -267,14 +286,15 @@ static int32_t gmm_block_impl(const orc_gmm_cfg *c, uint32_t t, int32_t block, i
                 accepted[i] = 0;
         return 0;
     }
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : count)
     for (int64_t i = 0; i < n; ++i) {
         double phi[3 * 64], prop[3 * 64], gl[3 * 64], gp[3 * 64], glp[3 * 64], gpp[3 * 64];
         double xi[64];
+        const uint32_t pid = (uint32_t)(ids ? ids[i] : i);
         get_phi(pop, n, D, i, phi);
         for (int m = 0; m < dim; m += 2) {
             double z[2];
-            orc_normal2(c->seed, (uint32_t)i, t, tag, (uint32_t)(64 * sweep + m / 2), c->problem,
-                        z);
+            orc_normal2(c->seed, pid, t, tag, (uint32_t)(64 * sweep + m / 2), c->problem, z);
             xi[m] = z[0];
             if (m + 1 < dim)
                 xi[m + 1] = z[1];
@@ -298,6 +318,9 @@ static int32_t gmm_block_impl(const orc_gmm_cfg *c, uint32_t t, int32_t block, i
         double llp = orc_gmm_loglik_grad(prop, K, y, nd, mala ? gp : NULL);
         double lpp = orc_gmm_logprior(c, prop);
         double logr = tempered(lpp, llp, alpha) - cur;
+        /* size of the terms behind log r (for the decision-margin record) */
+        double mag = 1.0 + fabs(lp[i]) + fabs(lpp) +
+                     (alpha == 0.0 ? 0.0 : alpha * (fabs(ll[i]) + fabs(llp)));
         if (mala) {
             orc_gmm_logprior_grad(c, prop, gpp);
             double fwd = 0.0, bwd = 0.0;
@@ -310,9 +333,10 @@ static int32_t gmm_block_impl(const orc_gmm_cfg *c, uint32_t t, int32_t block, i
             }
             /* log q(phi | phi') - log q(phi' | phi) */
             logr += (fwd - bwd) / (2.0 * h2);
+            mag += (fwd + bwd) / (2.0 * h2);
         }
         uint32_t w[4];
-        orc_draw_words(c->seed, (uint32_t)i, t, ORC_TAG_MH_ACCEPT, (uint32_t)(4 * sweep + block),
+        orc_draw_words(c->seed, pid, t, ORC_TAG_MH_ACCEPT, (uint32_t)(4 * sweep + block),
                        c->problem, w);
         double logu = log(orc_u53(w[0], w[1]));
         int acc = logu <= logr;
@@ -320,6 +344,8 @@ static int32_t gmm_block_impl(const orc_gmm_cfg *c, uint32_t t, int32_t block, i
             logr_out[i] = logr;
         if (logu_out)
             logu_out[i] = logu;
+        if (scale_out)
+            scale_out[i] = mag;
         if (acc) {
             put_phi(pop, n, D, i, prop);
             ll[i] = llp;
@@ -339,7 +365,7 @@ int32_t orc_gmm_block(const orc_gmm_cfg *c, uint32_t t, int32_t block, int32_t s
                       double *ll, double *lp, double *grad, int32_t *accepted)
 {
     return gmm_block_impl(c, t, block, sweep, alpha, scale, y, nd, pop, ll, lp, grad, accepted,
-                          NULL, NULL);
+                          NULL, NULL, NULL, NULL, 0);
 }
 
 /* Same, also returning log r and log u of every particle's decision. */
@@ -349,22 +375,23 @@ int32_t orc_gmm_block_trace(const orc_gmm_cfg *c, uint32_t t, int32_t block, int
                             double *logr_out, double *logu_out)
 {
     return gmm_block_impl(c, t, block, sweep, alpha, scale, y, nd, pop, ll, lp, grad, accepted,
-                          logr_out, logu_out);
+                          logr_out, logu_out, NULL, NULL, 0);
 }
 
-/*
- * Complete sampler (Algorithm "gmm") over T tempering steps with
- * alpha[0..T] (alpha[0] = 0) and per-step block scales scales[t][3]
- * (random-walk standard deviations, or MALA step sizes).
- *   step t: dalpha = alpha_t - alpha_{t-1} (0 when alpha_t == 0); reweight;
- *   normalise (dlogZ = L_t - L_{t-1}, L after a resample = log N); resample
- *   when ESS < threshold N; `sweeps` passes of the mu, eta, z blocks at
- *   alpha_t; record.
- * hist[t][0..8] (t = 0..T) = ESS, resampled, dlogZ, logZ, L, accepts of the
- * three blocks, U_t = sum_i W_i l_i (path-sampling integrand, Eq.
- * path_import).  Final population written to pop_final / ll / lp / lw when
- * non-NULL.  Returns the direct estimate log Z (Eq. smc-ds).
- */
+/* Same for the particles ids[0..m-1] only: the arrays hold m columns,
+   column q being particle ids[q] with that particle's random numbers (the
+   blocks act on each particle independently, so this equals the columns of
+   the whole-population update). */
+int32_t orc_gmm_block_trace_ids(const orc_gmm_cfg *c, uint32_t t, int32_t block, int32_t sweep,
+                                double alpha, double scale, const double *y, int64_t nd,
+                                const int64_t *ids, int64_t m, double *pop, double *ll,
+                                double *lp, double *grad, int32_t *accepted, double *logr_out,
+                                double *logu_out)
+{
+    return gmm_block_impl(c, t, block, sweep, alpha, scale, y, nd, pop, ll, lp, grad, accepted,
+                          logr_out, logu_out, NULL, ids, m);
+}
+
 /* Path-sampling estimate of log(Z_1 / Z_0) (Section 5.2, Eq. path_est): the
    trapezoidal rule over the annealing schedule alpha[0..T] applied to the
    importance-sampling integrands U[0..T] (Eq. path_import), summed in t
@@ -377,6 +404,31 @@ double orc_path_sampling(const double *alpha, const double *U, int64_t len)
     return ps;
 }
 
+/*
+ * Complete sampler (Algorithm "gmm") over T tempering steps with
+ * alpha[0..T] (alpha[0] = 0) and per-step block scales scales[t][3]
+ * (random-walk standard deviations, or MALA step sizes).
+ *   step t: dalpha = alpha_t - alpha_{t-1} (0 when alpha_t == 0); reweight;
+ *   normalise (dlogZ = L_t - L_{t-1}, L after a resample = log N); resample
+ *   when ESS < threshold N; `sweeps` passes of the mu, eta, z blocks at
+ *   alpha_t; record.
+ * hist[t][0..9] (t = 0..T) = ESS, resampled, dlogZ, logZ, L, accepts of the
+ * three blocks, U_t = sum_i W_i l_i (path-sampling integrand, Eq.
+ * path_import) and the running path-sampling estimate (Eq. path_est).
+ * hist[t][10..12] record how close the step's decisions came to their
+ * thresholds, so that a comparison of two independent runs can tell a
+ * legitimate rounding-order flip from a mistake:
+ *   10: min over the Metropolis decisions of |log r - log u| divided by the
+ *       size of the terms behind log r (1 + |lp| + |lp'| + alpha (|l| + |l'|)
+ *       + the MALA proposal terms);
+ *   11: |ESS - tau N| / (tau N) of the resampling decision (+inf when
+ *       tau >= 1 or tau <= 0 decides it);
+ *   12: min over the slots of the distance from u_i S to the nearer of the
+ *       two cumulative weights bracketing it, divided by S (+inf when the
+ *       step does not resample).
+ * Final population written to pop_final / lw_final when non-NULL.  Returns
+ * the direct estimate log Z (Eq. smc-ds).
+ */
 double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
                    const double *alpha, const double *scales, double *hist, double *pop_final,
                    double *lw_final)
@@ -392,8 +444,14 @@ double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
     double *tmp = (double *)malloc(sizeof(double) * (size_t)n);
     double *lw = (double *)calloc((size_t)n, sizeof(double));
     int32_t *anc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *logr = (double *)malloc(sizeof(double) * (size_t)n);
+    double *logu = (double *)malloc(sizeof(double) * (size_t)n);
+    double *mag = (double *)malloc(sizeof(double) * (size_t)n);
+    double *S = (double *)malloc(sizeof(double) * (size_t)n);
+    double *us = (double *)malloc(sizeof(double) * (size_t)n);
     orc_gmm_init(c, y, nd, pop, ll, lp);
     if (c->move_kind == 1)
+#pragma omp parallel for schedule(dynamic, 16)
         for (int64_t i = 0; i < n; ++i) {
             double phi[3 * 64], g[3 * 64];
             get_phi(pop, n, D, i, phi);
@@ -414,6 +472,7 @@ double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
         hist[0] = (double)n;
         hist[4] = Lprev;
         hist[8] = U_prev;
+        hist[10] = hist[11] = hist[12] = INFINITY;
     }
     for (int32_t t = 1; t <= T; ++t) {
         double a = alpha[t];
@@ -429,11 +488,20 @@ double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
         logZ += dlogz;
         Lprev = nz[0];
         resampled = orc_resample_flag(nz[2], n, c->threshold);
+        double flag_margin = INFINITY, anc_margin = INFINITY, mh_margin = INFINITY;
+        if (c->threshold > 0.0 && c->threshold < 1.0)
+            flag_margin = fabs(nz[2] - c->threshold * (double)n) / (c->threshold * (double)n);
         if (resampled) {
-            if (orc_resample(c->scheme, c->seed, (uint32_t)t, c->problem, lw, n, anc, NULL,
-                             NULL) != 0) {
+            if (orc_resample(c->scheme, c->seed, (uint32_t)t, c->problem, lw, n, anc, S, us) != 0) {
                 logZ = NAN;
                 break;
+            }
+            const double tot = S[n - 1];
+            for (int64_t i = 0; i < n; ++i) {
+                const double x = us[i] * tot;
+                const double lo = anc[i] > 0 ? S[anc[i] - 1] : 0.0;
+                const double d = fmin(fabs(x - lo), fabs(S[anc[i]] - x)) / tot;
+                anc_margin = fmin(anc_margin, d);
             }
             for (int q = 0; q < D; ++q)
                 for (int64_t i = 0; i < n; ++i) {
@@ -454,15 +522,23 @@ double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
         int32_t acc[3] = {0, 0, 0};
         for (int s = 0; s < (c->sweeps > 0 ? c->sweeps : 1); ++s)
             for (int b = 0; b < 3; ++b)
+            {
                 acc[b] += gmm_block_impl(c, (uint32_t)t, b, s, a, scales[3 * t + b], y, nd, pop,
-                                         ll, lp, grad, NULL, NULL, NULL);
+                                         ll, lp, grad, NULL, logr, logu, mag, NULL, 0);
+                if (b < 2 || K > 1)
+                    for (int64_t i = 0; i < n; ++i)
+                        mh_margin = fmin(mh_margin, fabs(logr[i] - logu[i]) / mag[i]);
+            }
         /* U_t = sum_i W_t^(i) l(theta_t^(i)) (Eq. path_import: under the
            geometric path the integrand d log q_alpha / d alpha is the
            log-likelihood) and one trapezoid of Eq. path_est */
         double L = resampled ? log((double)n) : nz[0];
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            tmp[i] = exp(lw[i] - L) * ll[i];
         orc_ksum u = {0.0, 0.0};
         for (int64_t i = 0; i < n; ++i)
-            orc_ks_add(&u, exp(lw[i] - L) * ll[i]);
+            orc_ks_add(&u, tmp[i]);
         const double U = orc_ks_val(&u);
         ps += 0.5 * (a - a_alpha_prev_ps) * (U + U_prev);
         U_prev = U;
@@ -479,6 +555,9 @@ double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
             h[7] = acc[2];
             h[8] = U;
             h[9] = ps;
+            h[10] = mh_margin;
+            h[11] = flag_margin;
+            h[12] = anc_margin;
         }
     }
     if (pop_final)
@@ -486,6 +565,6 @@ double orc_gmm_run(const orc_gmm_cfg *c, const double *y, int64_t nd, int32_t T,
     if (lw_final)
         memcpy(lw_final, lw, sizeof(double) * (size_t)n);
     free(pop); free(pop2); free(grad); free(grad2); free(ll); free(lp); free(tmp); free(lw);
-    free(anc);
+    free(anc); free(logr); free(logu); free(mag); free(S); free(us);
     return logZ;
 }

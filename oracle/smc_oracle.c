@@ -8,7 +8,10 @@
  * Every function follows the paper's definitions step by step, in the
  * paper's order, with plain loops, sequential fixed-order (Neumaier
  * compensated) sums and strict IEEE arithmetic (built with -O2
- * -ffp-contract=off, no fast-math).  Citations name the section, equation or
+ * -ffp-contract=off, no fast-math).  Loops whose iterations are independent
+ * (one particle each: draws, moves, gathers, the terms of a sum) may run on
+ * several threads (OpenMP); every sum is still taken by one thread in index
+ * order, so the results do not depend on the number of threads.  Citations name the section, equation or
  * algorithm of Zhou, "vSMC: Parallel Sequential Monte Carlo in C++"
  * (arXiv:1306.5583).  Readings of points the paper leaves open are listed in
  * the design notes; each is restated where it is used.
@@ -19,11 +22,17 @@
  * hi32(seed)).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include "oracle_internal.h"
+
+/* Threads for the independent loops (the benchmark's CPU baseline times
+   one and all); the results are the same for any count. */
+void orc_set_threads(int32_t n) { omp_set_num_threads(n > 0 ? n : 1); }
+int32_t orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10                                                             */
@@ -196,9 +205,14 @@ static double lse_scaled(const double *lw, int64_t n, double scale)
     double m = orc_max(lw, n);
     if (m == -INFINITY)
         return -INFINITY;
+    double *e = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        e[i] = exp(scale * (lw[i] - m));
     ksum acc = {0.0, 0.0};
     for (int64_t i = 0; i < n; ++i)
-        ks_add(&acc, exp(scale * (lw[i] - m)));
+        ks_add(&acc, e[i]);
+    free(e);
     return scale * m + log(ks_val(&acc));
 }
 
@@ -255,18 +269,27 @@ void orc_resample_uniforms(int scheme, uint64_t seed, uint32_t t, uint32_t p, in
         for (int64_t i = 0; i < n; ++i)
             u[i] = ((double)i + U) / (double)n;
     } else if (scheme == ORC_RS_STRATIFIED) {
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
-            draw(seed, (uint32_t)i, t, ORC_TAG_RESAMPLE, 0, p, w);
-            u[i] = ((double)i + orc_u53(w[0], w[1])) / (double)n;
+            uint32_t wi[4];
+            draw(seed, (uint32_t)i, t, ORC_TAG_RESAMPLE, 0, p, wi);
+            u[i] = ((double)i + orc_u53(wi[0], wi[1])) / (double)n;
         }
     } else {
         double *G = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+        double *E = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k <= n; ++k) {
+            uint32_t wk[4];
+            draw(seed, (uint32_t)k, t, ORC_TAG_RESAMPLE, 1, p, wk);
+            E[k] = -log(orc_u53(wk[0], wk[1]));
+        }
         ksum acc = {0.0, 0.0};
         for (int64_t k = 0; k <= n; ++k) {
-            draw(seed, (uint32_t)k, t, ORC_TAG_RESAMPLE, 1, p, w);
-            ks_add(&acc, -log(orc_u53(w[0], w[1])));
+            ks_add(&acc, E[k]);
             G[k] = ks_val(&acc);
         }
+        free(E);
         for (int64_t i = 0; i < n; ++i)
             u[i] = G[i] / G[n];
         free(G);
@@ -288,9 +311,12 @@ int orc_ancestors(const double *lw, int64_t n, const double *u, int32_t *anc,
     if (!(m > -INFINITY) || !isfinite(m))
         return -1;
     double *S = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j)
+        S[j] = exp(lw[j] - m);
     ksum acc = {0.0, 0.0};
     for (int64_t j = 0; j < n; ++j) {
-        ks_add(&acc, exp(lw[j] - m));
+        ks_add(&acc, S[j]);
         S[j] = ks_val(&acc);
     }
     double tot = S[n - 1];
@@ -365,12 +391,17 @@ void orc_weighted_mean(const double *x, int64_t dim, const double *lw, int64_t n
                        double *est)
 {
     double L = orc_lse(lw, n);
+    double *W = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        W[i] = exp(lw[i] - L);
     for (int64_t c = 0; c < dim; ++c) {
         ksum acc = {0.0, 0.0};
         for (int64_t i = 0; i < n; ++i)
-            ks_add(&acc, exp(lw[i] - L) * x[c * n + i]);
+            ks_add(&acc, W[i] * x[c * n + i]);
         est[c] = ks_val(&acc);
     }
+    free(W);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -423,6 +454,7 @@ static double pf_loglik(const orc_pf_cfg *c, double px, double py, const double 
 void orc_pf_init(const orc_pf_cfg *c, const double y0[2], double *x, double *lw)
 {
     int64_t n = c->n;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double xi[4];
         if (c->fp32_state) {
@@ -455,6 +487,7 @@ void orc_pf_move(const orc_pf_cfg *c, uint32_t t, const double yt[2], const doub
                  const double *lw_in, int lw_reset, double *x_out, double *lw_out)
 {
     int64_t n = c->n;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double px = x_in[0 * n + i], py = x_in[1 * n + i];
         double vx = x_in[2 * n + i], vy = x_in[3 * n + i];
@@ -491,9 +524,11 @@ void orc_pf_move(const orc_pf_cfg *c, uint32_t t, const double yt[2], const doub
 void orc_gather(const double *x_in, int64_t dim, int64_t n, const int32_t *anc,
                 double *x_out)
 {
-    for (int64_t k = 0; k < dim; ++k)
+    for (int64_t k = 0; k < dim; ++k) {
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i)
             x_out[k * n + i] = x_in[k * n + anc[i]];
+    }
 }
 
 /*

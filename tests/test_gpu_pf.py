@@ -50,12 +50,16 @@ def _gathered(state, anc, resampled):
     return state[:, anc] if resampled else state
 
 
-def _lockstep(lib, orc, n, T, seed, scheme, fp32=False, obs_nu=10.0, threshold=0.5, data_seed=7):
+def _lockstep(lib, orc, n, T, seed, scheme, fp32=False, obs_nu=10.0, threshold=0.5, data_seed=7,
+              fused_monitor=False):
     """Runs the GPU filter step by step; at every step the oracle recomputes
-    the step from the GPU's input state and the outputs are compared."""
+    the step from the GPU's input state and the outputs are compared.  With
+    fused_monitor the monitor of step t rides on the move of step t + 1 and
+    is completed by its normalisation (the benchmark's launch sequence);
+    otherwise each step calls the standalone monitor."""
     pkg, L = lib
-    _say("lockstep n=%d T=%d seed=%d scheme=%s fp32=%s nu=%s thr=%s" %
-         (n, T, seed, scheme, fp32, obs_nu, threshold))
+    _say("lockstep n=%d T=%d seed=%d scheme=%s fp32=%s nu=%s thr=%s fused_monitor=%s" %
+         (n, T, seed, scheme, fp32, obs_nu, threshold, fused_monitor))
     model = synth.CVModel(obs_nu=obs_nu)
     _, y = synth.pf_trajectory(T, data_seed, model)
     pf = pkg.ParticleFilter(n, y, seed=seed, scheme=scheme, fp32_state=fp32, obs_nu=obs_nu,
@@ -73,11 +77,13 @@ def _lockstep(lib, orc, n, T, seed, scheme, fp32=False, obs_nu=10.0, threshold=0
     logz_scale = 0.0
     flips = 0
     resampled = False
+    est_prev = None
     for t in range(T):
         if t > 0:
             x_in = _gathered(x_g, anc_g, resampled)
             lw_in = lw_g
             pf._margs.obs_index = t
+            pf._margs.monitor_step = t - 1 if fused_monitor else -1
             L.smc_move(ctx, t, pf._margs)
             torch.cuda.synchronize()
             x_g = pf.state().double().cpu().numpy()
@@ -91,6 +97,11 @@ def _lockstep(lib, orc, n, T, seed, scheme, fp32=False, obs_nu=10.0, threshold=0
         # normalisation on the GPU's weights
         L.smc_ess(ctx, t)
         sc = pf.scalars_host()
+        if fused_monitor and t > 0:
+            # the monitor of step t - 1, completed alongside this normalisation
+            hist = pf.history.cpu().numpy()
+            assert_close_l1(hist[t - 1, L.SMC_H_MON:L.SMC_H_MON + 4], est_prev[0], est_prev[1],
+                            rtol, "fused monitor t=%d" % (t - 1))
         Lo, L2o, esso = orc.normalise(lw_g)
         assert abs(sc[L.SMC_S_L] - Lo) <= 1e-12 * max(1.0, abs(Lo)), (t, sc[L.SMC_S_L], Lo)
         assert abs(sc[L.SMC_S_ESS] - esso) <= 1e-12 * esso, (t, sc[L.SMC_S_ESS], esso)
@@ -110,14 +121,18 @@ def _lockstep(lib, orc, n, T, seed, scheme, fp32=False, obs_nu=10.0, threshold=0
                 assert sc[L.SMC_S_U] == orc.u53(int(w[0]), int(w[1]))
             flips += assert_ancestors(anc_g, anc_o, S_o, u_o, what="anc t=%d" % t)
         # monitor after resampling
+        xm = _gathered(x_g, anc_g, resampled)
+        lwm = np.zeros(n) if resampled else lw_g
+        est_o = orc.weighted_mean(xm, lwm)
+        mon_scale = np.abs(xm).max(axis=1) * 4
+        if fused_monitor and t < T - 1:
+            est_prev = (est_o, mon_scale)
+            continue
         out = torch.zeros(4, dtype=torch.float64, device="cuda")
         L.smc_monitor(ctx, t, out.data_ptr())
         torch.cuda.synchronize()
         est_g = out.cpu().numpy()
-        xm = _gathered(x_g, anc_g, resampled)
-        lwm = np.zeros(n) if resampled else lw_g
-        est_o = orc.weighted_mean(xm, lwm)
-        assert_close_l1(est_g, est_o, np.abs(xm).max(axis=1) * 4, rtol, "monitor t=%d" % t)
+        assert_close_l1(est_g, est_o, mon_scale, rtol, "monitor t=%d" % t)
         hist = pf.history.cpu().numpy()
         assert np.array_equal(hist[t, L.SMC_H_MON:L.SMC_H_MON + 4], est_g)
     pf.check()
@@ -152,12 +167,25 @@ def test_small_and_tile_edges(lib, orc, n):
 
 
 def test_full_size_lockstep_steps(lib, orc):
-    # the benchmark's particle count: N = 2^22, a few full steps lock-step
-    _lockstep(lib, orc, 1 << 22, 3, 2, "systematic")
+    # the benchmark's workload: N = 2^22, its launch sequence (monitor fused
+    # into the next move), a few full steps in lock-step
+    _lockstep(lib, orc, 1 << 22, 4, 2, "systematic", fused_monitor=True)
 
 
 def test_full_size_multinomial(lib, orc):
-    _lockstep(lib, orc, 1 << 22, 2, 3, "multinomial", threshold=1.0)
+    _lockstep(lib, orc, 1 << 22, 3, 3, "multinomial", threshold=1.0, fused_monitor=True)
+
+
+@pytest.mark.parametrize("scheme", ["systematic", "multinomial"])
+def test_full_size_fp32_state(lib, orc, scheme):
+    # the FP32-state variant of the same workload (threshold 1: every step
+    # resamples, so the gathered FP32 path runs on each)
+    _lockstep(lib, orc, 1 << 22, 3, 6, scheme, fp32=True, threshold=1.0, fused_monitor=True)
+
+
+def test_lockstep_fused_monitor_small(lib, orc):
+    # the benchmark's launch sequence over a ragged population, many steps
+    _lockstep(lib, orc, 70001, 20, 12, "systematic", fused_monitor=True)
 
 
 def test_end_to_end_c0(lib, orc):

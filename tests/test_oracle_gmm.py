@@ -263,3 +263,68 @@ def test_path_sampling_matches_direct_estimate_k1(orc):
     se = ps.std(ddof=1) / math.sqrt(ps.size)
     assert abs(ps.mean() - ref) <= bound + 4 * se + 0.02, (ps.mean(), ref, bound, se)
     assert abs(ds.mean() - ref) < 4 * ds.std(ddof=1) / math.sqrt(ds.size) + 0.02
+
+
+@pytest.mark.parametrize("move", ["rw", "mala"])
+def test_particle_subset_equals_population_columns(orc, move):
+    # the sampled-column forms used at sizes the oracle cannot replay whole:
+    # particle ids pick the random numbers, so a subset reproduces exactly
+    # the corresponding columns of the whole-population update
+    K, n, nd = 3, 700, 50
+    y = synth.gmm_data(nd, [-2.0, 0.5, 2.5], 2.0, [1, 1, 1], 9)
+    cfg = orc.gmm_cfg(n, 13, K, move=move)
+    pop, ll, lp = orc.gmm_init(cfg, y)
+    ids = np.array([0, 3, 64, 65, 311, 699])
+    p2, l2, q2 = orc.gmm_init_ids(cfg, y, ids)
+    assert np.array_equal(p2, pop[:, ids]) and np.array_equal(l2, ll[ids])
+    assert np.array_equal(q2, lp[ids])
+    grad = None
+    if move == "mala":
+        grad = np.stack([orc.gmm_loglik(pop[:, i], K, y, grad=True)[1] for i in range(n)], axis=1)
+    for b in range(3):
+        full = orc.gmm_block_trace(cfg, 5, b, 0, 0.4, 0.1, y, pop, ll, lp, grad)
+        sub = orc.gmm_block_trace_ids(cfg, 5, b, 0, 0.4, 0.1, y, ids, pop[:, ids], ll[ids],
+                                      lp[ids], None if grad is None else grad[:, ids])
+        for u, v in zip(full, sub):
+            if u is not None:
+                assert np.array_equal(u[..., ids], v)
+        pop, ll, lp, grad = full[:4]
+
+
+def test_run_records_decision_margins(orc):
+    # the whole run's margin columns: the Metropolis margin equals the
+    # smallest |log r - log u| / size over the replayed blocks, the resample
+    # margin |ESS - tau N| / tau N, and no margin is recorded at step 0
+    K, n, nd, T = 2, 400, 30, 4
+    y = synth.gmm_data(nd, [-1.0, 2.0], 2.0, [1, 1], 4)
+    alphas = np.linspace(0.0, 1.0, T + 1) ** 2
+    scales = np.full((T + 1, 3), 0.2)
+    cfg = orc.gmm_cfg(n, 21, K, threshold=0.9)
+    _, hist, _, _ = orc.gmm_run(cfg, y, alphas, scales)
+    assert hist.shape == (T + 1, 13)
+    assert np.all(np.isinf(hist[0, 10:13]))
+    assert np.all(hist[1:, 10] >= 0) and np.all(np.isfinite(hist[1:, 10]))
+    assert np.allclose(hist[1:, 11], np.abs(hist[1:, 0] - 0.9 * n) / (0.9 * n), rtol=0, atol=1e-15)
+    rs = hist[1:, 1] != 0
+    assert np.all(np.isinf(hist[1:, 12][~rs]))
+    assert np.all((hist[1:, 12][rs] >= 0) & (hist[1:, 12][rs] <= 0.5))
+    # step 1 replayed by hand: min over the blocks of the recorded margins
+    pop, ll, lp = orc.gmm_init(cfg, y)
+    lw = orc.gmm_reweight(np.zeros(n), ll, alphas[1], False)
+    L, _, ess = orc.normalise(lw)
+    if orc.resample_flag(ess, n, 0.9):
+        anc, _, _ = orc.resample("systematic", 21, 1, lw)
+        pop, ll, lp = pop[:, anc], ll[anc], lp[anc]
+    m = np.inf
+    for b in range(3):
+        before_ll, before_lp = ll.copy(), lp.copy()
+        pop, ll, lp, _, acc, logr, logu = orc.gmm_block_trace(cfg, 1, b, 0, alphas[1], 0.2, y,
+                                                              pop, ll, lp)
+        # the size behind log r: log prior and tempered likelihood of both points
+        prop_ll = np.where(acc == 1, ll, np.nan)
+        ok = acc == 1
+        if ok.any():
+            size = (1 + np.abs(before_lp[ok]) + np.abs(lp[ok])
+                    + alphas[1] * (np.abs(before_ll[ok]) + np.abs(prop_ll[ok])))
+            m = min(m, float(np.min(np.abs(logr[ok] - logu[ok]) / size)))
+    assert hist[1, 10] <= m

@@ -185,3 +185,19 @@ def test_fp32_state_close_to_fp64(orc):
     assert np.array_equal(x32.astype(np.float32).astype(np.float64), x32)
     # the FP32 variant draws its normals differently; compare distributions only
     assert abs(x32.std() - x64.std()) < 0.1
+
+
+@pytest.mark.parametrize("scheme", ["systematic", "multinomial", "stratified"])
+def test_results_do_not_depend_on_threads(orc, scheme):
+    # per-particle loops may run on several threads, every sum stays
+    # sequential in index order: one thread and many give the same bits
+    _, y = synth.pf_trajectory(6, 3)
+    runs = []
+    n0 = orc.max_threads()
+    for th in (1, 4):
+        orc.set_threads(th)
+        runs.append(orc.pf_run(orc.pf_cfg(20011, 2, scheme=scheme), y))
+    orc.set_threads(n0)
+    assert runs[0][0] == runs[1][0]
+    for a, b in zip(runs[0][1:], runs[1][1:]):
+        assert np.array_equal(a, b)
