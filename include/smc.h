@@ -292,6 +292,31 @@ smc_status smc_gmm_loglik_grad(const double *mu, const double *eta, const double
                                int64_t n, int32_t K, const double *y, int64_t n_data,
                                double *loglik, double *grad, void *hip_stream);
 
+/* Resampling of caller-held log-weights in one call (Section 2.1: the
+ * effective sample size, the resampling decision and the replication
+ * numbers R_j with sum N; Eq. resample): normalises lw[n] (unnormalised
+ * log-weights) in a fixed order, decides (force != 0: always; else ESS <
+ * threshold * n, threshold >= 1 always, <= 0 never) and, when the decision
+ * fires, writes the sorted ancestors of `scheme` (SMC_RS_*) drawn from the
+ * Philox stream of (seed, step, problem) -- the same ancestors smc_resample
+ * writes for a context with these weights -- to ancestors[n]; otherwise
+ * leaves ancestors untouched.  summary[5] receives {L = log sum exp lw,
+ * L2 = log sum exp 2 lw, ESS, 1 if resampled else 0, device error bits
+ * (SMC_DEVERR_*; non-zero means no ancestors were written)}.
+ * lw: device double[n], 32-byte aligned, read only; ancestors: device
+ * int32[n]; summary: device double[5]; workspace: device memory of at least
+ * smc_resample_weights_workspace(n, scheme) bytes, 256-byte aligned, owned
+ * by the caller, no initial contents needed, not to be shared by calls that
+ * overlap.  Everything is enqueued on hip_stream (the current device's);
+ * nothing synchronises.  Errors: SMC_ERR_INVALID_ARG (null or misaligned
+ * pointer, n outside [1, 2^31 - 1], unknown scheme, workspace too small),
+ * SMC_ERR_DEVICE (no gfx950 device current, launch failure). */
+smc_status smc_resample_weights_workspace(int64_t n, int32_t scheme, size_t *bytes);
+smc_status smc_resample_weights(const double *lw, int64_t n, int32_t scheme, double threshold,
+                                int32_t force, uint64_t seed, uint32_t step, uint32_t problem,
+                                int32_t *ancestors, double *summary, void *workspace,
+                                size_t workspace_bytes, void *hip_stream);
+
 /* Raw Philox4x32-10 words of the library's counter-based streams (the
  * per-particle engines of Section 4.1, "Generating random numbers"):
  * out[4*i + w] = word w of the call with counter (i, step, tag<<16 | call,

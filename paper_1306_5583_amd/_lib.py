@@ -121,6 +121,9 @@ def load() -> ctypes.CDLL:
         "smc_last_error": (ctypes.c_char_p, [_vp]),
         "smc_gmm_loglik_grad": (st, [_vp, _vp, _vp, _i64, _i32, _vp, _i64, _vp, _vp, _vp]),
         "smc_draw_words": (st, [_u64, _u32, _u32, _u32, _u32, _i64, _vp, _vp]),
+        "smc_resample_weights_workspace": (st, [_i64, _i32, P(ctypes.c_size_t)]),
+        "smc_resample_weights": (st, [_vp, _i64, _i32, _d, _i32, _u64, _u32, _u32, _vp, _vp,
+                                      _vp, ctypes.c_size_t, _vp]),
         "smc_profile_start": (st, [_vp, _i32]),
         "smc_profile_read": (st, [_vp, P(ctypes.c_float), _i32, P(_i32)]),
         "smc_batch_table_size": (st, [P(smc_batch_problem), _i32, P(ctypes.c_size_t)]),
@@ -149,7 +152,9 @@ def exported_symbols():
             "smc_destroy", "smc_set_stream", "smc_init", "smc_move", "smc_reweight", "smc_ess",
             "smc_resample", "smc_monitor", "smc_gather", "smc_copy_from", "smc_current_state",
             "smc_read_scalars", "smc_check", "smc_last_error", "smc_gmm_loglik_grad",
-            "smc_draw_words", "smc_profile_start", "smc_profile_read", "smc_batch_table_size", "smc_batch_create", "smc_batch_destroy",
+            "smc_draw_words", "smc_resample_weights_workspace", "smc_resample_weights",
+            "smc_profile_start", "smc_profile_read", "smc_batch_table_size",
+            "smc_batch_create", "smc_batch_destroy",
             "smc_batch_autotune", "smc_batch_waves", "smc_batch_init", "smc_batch_step",
             "smc_batch_capture", "smc_batch_replay", "smc_batch_check", "smc_batch_last_error"]
 
@@ -286,6 +291,20 @@ def smc_gmm_loglik_grad(mu_ptr, eta_ptr, z_ptr, n, K, y_ptr, n_data, ll_ptr, gra
 def smc_draw_words(seed, step, tag, call, problem, n, out_ptr, stream_handle):
     _check(load().smc_draw_words(seed, step, tag, call, problem, n, _vp(out_ptr),
                                  _vp(stream_handle)), "smc_draw_words")
+
+
+def smc_resample_weights_workspace(n, scheme):
+    b = ctypes.c_size_t()
+    _check(load().smc_resample_weights_workspace(n, scheme, ctypes.byref(b)),
+           "smc_resample_weights_workspace")
+    return b.value
+
+
+def smc_resample_weights(lw_ptr, n, scheme, threshold, force, seed, step, problem, anc_ptr,
+                         summary_ptr, ws_ptr, ws_bytes, stream_handle):
+    _check(load().smc_resample_weights(_vp(lw_ptr), n, scheme, threshold, force, seed, step,
+                                       problem, _vp(anc_ptr), _vp(summary_ptr), _vp(ws_ptr),
+                                       ws_bytes, _vp(stream_handle)), "smc_resample_weights")
 
 
 def smc_profile_start(ctx, count):

@@ -65,6 +65,33 @@ Workspace plan_workspace(const smc_config &cfg)
     return w;
 }
 
+Workspace plan_resample_workspace(int64_t n, int32_t scheme, size_t *scalars)
+{
+    Workspace w{};
+    const int64_t ntiles = ceil_div(n, TILE);
+    const int64_t gtiles = ceil_div(n + 1, TILE);
+    size_t off = 0;
+    *scalars = off;
+    off = align256(off + sizeof(double) * SMC_SCALARS_LEN);
+    w.partials = off;
+    off = align256(off + sizeof(TilePartial) * (size_t)ntiles);
+    w.prefix = off;
+    off = align256(off + sizeof(double) * (size_t)(ntiles + 1));
+    w.counters = off;
+    off = align256(off + sizeof(int32_t) * 16);
+    w.mon = w.cf = w.cf_tiles = off;  // not used by the one-shot resampling
+    if (scheme == SMC_RS_MULTINOMIAL) {
+        w.g = off;
+        off = align256(off + sizeof(double) * (size_t)(n + 1));
+        w.gtile = off;
+        off = align256(off + sizeof(double) * (size_t)gtiles);
+        w.gprefix = off;
+        off = align256(off + sizeof(double) * (size_t)(gtiles + 1));
+    }
+    w.total = off;
+    return w;
+}
+
 Prob prob_from(const smc_config &cfg, const smc_buffers &buf, const Workspace &ws,
                       void *s0, void *s1)
 {
@@ -659,6 +686,84 @@ smc_status smc_gmm_loglik_grad(const double *mu, const double *eta, const double
     const hipError_t e = launch_gmm_loglik_grad(mu, eta, z, n, K, y, n_data, loglik, grad,
                                                 static_cast<hipStream_t>(hip_stream));
     return e == hipSuccess ? SMC_OK : SMC_ERR_DEVICE;
+}
+
+static smc_status resample_weights_args(const double *lw, int64_t n, int32_t scheme,
+                                        int32_t *ancestors, double *summary)
+{
+    if (!lw || !ancestors || !summary || n < 1 || n > 0x7FFFFFFFLL)
+        return SMC_ERR_INVALID_ARG;
+    if (scheme != SMC_RS_MULTINOMIAL && scheme != SMC_RS_SYSTEMATIC &&
+        scheme != SMC_RS_STRATIFIED)
+        return SMC_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(lw) % 32) != 0)  // tiles load four weights at once
+        return SMC_ERR_INVALID_ARG;
+    return SMC_OK;
+}
+
+smc_status smc_resample_weights_workspace(int64_t n, int32_t scheme, size_t *bytes)
+{
+    if (!bytes || n < 1 || n > 0x7FFFFFFFLL)
+        return SMC_ERR_INVALID_ARG;
+    size_t sc;
+    *bytes = plan_resample_workspace(n, scheme, &sc).total;
+    return SMC_OK;
+}
+
+// The one-shot resampling on a workspace the caller brings (or the static
+// scratch of the variant that allocates nothing): a context on the stack
+// whose buffers are the caller's log-weights and ancestors and whose
+// scalars, partials and counters live in the workspace.
+static smc_status resample_weights_on(const double *lw, int64_t n, int32_t scheme,
+                                      double threshold, int32_t force, uint64_t seed,
+                                      uint32_t step, uint32_t problem, int32_t *ancestors,
+                                      double *summary, char *ws, hipStream_t stream)
+{
+    Ctx c;
+    memset(&c.cfg, 0, sizeof(c.cfg));
+    c.cfg.abi_version = SMC_ABI_VERSION;
+    c.cfg.model = SMC_MODEL_CV_TRACK;
+    c.cfg.n = n;
+    c.cfg.scheme = static_cast<smc_scheme>(scheme);
+    c.cfg.threshold = threshold;
+    c.cfg.seed = seed;
+    c.cfg.problem_id = problem;
+    c.cfg.obs_scale = 1.0;
+    c.cfg.obs_nu = 1.0;
+    size_t sc_off;
+    c.ws = plan_resample_workspace(n, scheme, &sc_off);
+    memset(&c.buf, 0, sizeof(c.buf));
+    c.buf.log_weight = const_cast<double *>(lw);  // read only
+    c.buf.ancestors = ancestors;
+    c.buf.scalars = reinterpret_cast<double *>(ws + sc_off);
+    c.buf.workspace = ws;
+    c.buf.workspace_bytes = c.ws.total;
+    c.stream = stream;
+    c.n = n;
+    c.ntiles = ceil_div(n, TILE);
+    c.gtiles = ceil_div(n + 1, TILE);
+    const hipError_t e = launch_resample_weights(c, (int32_t)step, force, summary);
+    return e == hipSuccess ? SMC_OK : SMC_ERR_DEVICE;
+}
+
+smc_status smc_resample_weights(const double *lw, int64_t n, int32_t scheme, double threshold,
+                                int32_t force, uint64_t seed, uint32_t step, uint32_t problem,
+                                int32_t *ancestors, double *summary, void *workspace,
+                                size_t workspace_bytes, void *hip_stream)
+{
+    smc_status s = resample_weights_args(lw, n, scheme, ancestors, summary);
+    if (s != SMC_OK)
+        return s;
+    size_t sc;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % 256) != 0 ||
+        workspace_bytes < plan_resample_workspace(n, scheme, &sc).total)
+        return SMC_ERR_INVALID_ARG;
+    std::string err;
+    if ((s = device_ok(err)) != SMC_OK)
+        return s;
+    return resample_weights_on(lw, n, scheme, threshold, force, seed, step, problem, ancestors,
+                               summary, static_cast<char *>(workspace),
+                               static_cast<hipStream_t>(hip_stream));
 }
 
 smc_status smc_draw_words(uint64_t seed, uint32_t step, uint32_t tag, uint32_t call,

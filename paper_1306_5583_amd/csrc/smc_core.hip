@@ -1072,6 +1072,59 @@ hipError_t launch_resample_batch(const Prob *probs, const int2 *map, int64_t til
 }
 
 // ---------------------------------------------------------------------------
+// Resampling of a caller's log-weights in one call: per-tile partials of
+// lw, the normalisation, the resampling of the configured scheme, and a
+// five-value summary.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void lw_partials_kernel(const double *__restrict__ lw,
+                                                          int64_t n,
+                                                          TilePartial *__restrict__ part)
+{
+    __shared__ double red[NWAVES];
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+    double l[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t i = base + k * TPB + threadIdx.x;
+        l[k] = i < n ? lw[i] : -INFINITY;
+    }
+    tile_partial(l, part + blockIdx.x, red);
+}
+
+// summary = {L, L2, ESS, resampled (0/1), device error bits}
+__global__ void resample_summary_kernel(const double *__restrict__ scalars,
+                                        const int32_t *__restrict__ counters,
+                                        double *__restrict__ summary)
+{
+    if (threadIdx.x == 0) {
+        summary[0] = scalars[SMC_S_RESAMPLED] != 0.0 ? scalars[SMC_S_LPRE] : scalars[SMC_S_L];
+        summary[1] = scalars[SMC_S_L2];
+        summary[2] = scalars[SMC_S_ESS];
+        summary[3] = scalars[SMC_S_RESAMPLED];
+        summary[4] = (double)counters[CNT_ERR];
+    }
+}
+
+hipError_t launch_resample_weights(Ctx &c, int32_t step, int32_t force, double *summary)
+{
+    hipError_t e = launch_reset_scalars(c);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(lw_partials_kernel, dim3((unsigned)c.ntiles), dim3(TPB), 0, c.stream,
+                       (const double *)c.buf.log_weight, c.n, c.partials());
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    c.mon_pending_step = -1;
+    if ((e = launch_finalize(c, -1)) != hipSuccess)
+        return e;
+    if ((e = launch_resample(c, step, force)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(resample_summary_kernel, dim3(1), dim3(64), 0, c.stream, c.buf.scalars,
+                       (const int32_t *)c.counters(), summary);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Monitors: per-tile sums of w_i and w_i x_r,i (w_i = exp(lw_i - M), or 1
 // after a resample), column-major [1 + rows][ntiles], then one workgroup
 // combines the tiles in a fixed order.

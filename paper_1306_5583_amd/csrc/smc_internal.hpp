@@ -161,6 +161,9 @@ struct Ctx {
 enum Counter : int { CNT_ERR = 0, CNT_ACC0 = 1, CNT_ACC1 = 2, CNT_ACC2 = 3 };
 
 Workspace plan_workspace(const smc_config &cfg);
+// Workspace of the one-shot resampling of n log-weights (tile partials and
+// offsets, the scalar block at `scalars`, counters, multinomial staging).
+Workspace plan_resample_workspace(int64_t n, int32_t scheme, size_t *scalars);
 
 // Problem descriptor of a single-problem context (state[0] = the buffer the
 // state currently lives in).
@@ -181,6 +184,9 @@ hipError_t launch_gather(Ctx &c);
 hipError_t launch_copy_from(Ctx &c, int32_t *out);
 hipError_t launch_draw_words(uint64_t seed, uint32_t t, uint32_t tag, uint32_t j, uint32_t p,
                              int64_t n, uint32_t *out, hipStream_t stream);
+// Normalisation + resampling of c.buf.log_weight into c.buf.ancestors, then
+// the five-value summary (one-shot resampling entry points).
+hipError_t launch_resample_weights(Ctx &c, int32_t step, int32_t force, double *summary);
 
 // --- CV model launchers (smc_pf.hip) ---
 hipError_t launch_pf_init(Ctx &c);

@@ -175,3 +175,28 @@ def test_batch_host_validation(L):
     bad = _fake_problem(L, pf)
     bad.buf.workspace_bytes = 16
     assert create([bad]) == L.SMC_ERR_INVALID_ARG
+
+
+def test_resample_weights_arguments(L):
+    # the one-shot resampling entry points: workspace sizes, and argument
+    # errors answered before any device work (no GPU here: valid arguments
+    # end in SMC_ERR_DEVICE)
+    lib = L.load()
+    n = 1 << 20
+    sys_b = L.smc_resample_weights_workspace(n, 1)
+    mn_b = L.smc_resample_weights_workspace(n, 0)
+    assert 0 < sys_b < 1 << 20 and mn_b >= sys_b + 8 * (n + 1)
+    fake = 1 << 30        # aligned stand-in addresses, never dereferenced
+    cases = [
+        (0, n, 1, fake, fake, fake, sys_b),              # null log-weights
+        (fake, 0, 1, fake, fake, fake, sys_b),           # empty
+        (fake, n, 7, fake, fake, fake, sys_b),           # unknown scheme
+        (fake + 8, n, 1, fake, fake, fake, sys_b),       # misaligned log-weights
+        (fake, n, 1, fake, fake, fake, sys_b - 1),       # workspace too small
+        (fake, n, 1, fake, fake, fake + 64, sys_b),      # misaligned workspace
+    ]
+    for lw, nn, sch, anc, sm, ws, nb in cases:
+        assert lib.smc_resample_weights(lw, nn, sch, 0.5, 0, 1, 1, 0, anc, sm, ws, nb,
+                                        None) == L.SMC_ERR_INVALID_ARG
+    assert lib.smc_resample_weights(fake, n, 1, 0.5, 0, 1, 1, 0, fake, fake, fake, sys_b,
+                                    None) == L.SMC_ERR_DEVICE
