@@ -317,6 +317,25 @@ smc_status smc_resample_weights(const double *lw, int64_t n, int32_t scheme, dou
                                 int32_t *ancestors, double *summary, void *workspace,
                                 size_t workspace_bytes, void *hip_stream);
 
+/* The same resampling for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): arguments, results and errors as smc_resample_weights, but
+ * the workspace is the library's own static array of
+ * SMC_NOALLOC_SCRATCH_BYTES per device (obtained once per device, held
+ * until the process ends); the call allocates nothing.  Every call on a
+ * device shares that device's array and leaves its contents behind (the
+ * call clears what must start at zero itself), so calls that overlap on
+ * one device -- other streams, other threads -- race and must not be
+ * issued.  Inputs whose workspace (smc_resample_weights_workspace) exceeds
+ * the array are rejected with SMC_ERR_INVALID_ARG: systematic and
+ * stratified resampling up to about 100 million particles, multinomial up
+ * to about 500 thousand. */
+#define SMC_NOALLOC_SCRATCH_BYTES (4u << 20)
+smc_status smc_resample_weights_noalloc(const double *lw, int64_t n, int32_t scheme,
+                                        double threshold, int32_t force, uint64_t seed,
+                                        uint32_t step, uint32_t problem, int32_t *ancestors,
+                                        double *summary, void *hip_stream);
+
 /* Raw Philox4x32-10 words of the library's counter-based streams (the
  * per-particle engines of Section 4.1, "Generating random numbers"):
  * out[4*i + w] = word w of the call with counter (i, step, tag<<16 | call,

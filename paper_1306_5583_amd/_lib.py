@@ -124,6 +124,8 @@ def load() -> ctypes.CDLL:
         "smc_resample_weights_workspace": (st, [_i64, _i32, P(ctypes.c_size_t)]),
         "smc_resample_weights": (st, [_vp, _i64, _i32, _d, _i32, _u64, _u32, _u32, _vp, _vp,
                                       _vp, ctypes.c_size_t, _vp]),
+        "smc_resample_weights_noalloc": (st, [_vp, _i64, _i32, _d, _i32, _u64, _u32, _u32, _vp,
+                                              _vp, _vp]),
         "smc_profile_start": (st, [_vp, _i32]),
         "smc_profile_read": (st, [_vp, P(ctypes.c_float), _i32, P(_i32)]),
         "smc_batch_table_size": (st, [P(smc_batch_problem), _i32, P(ctypes.c_size_t)]),
@@ -153,6 +155,7 @@ def exported_symbols():
             "smc_resample", "smc_monitor", "smc_gather", "smc_copy_from", "smc_current_state",
             "smc_read_scalars", "smc_check", "smc_last_error", "smc_gmm_loglik_grad",
             "smc_draw_words", "smc_resample_weights_workspace", "smc_resample_weights",
+            "smc_resample_weights_noalloc",
             "smc_profile_start", "smc_profile_read", "smc_batch_table_size",
             "smc_batch_create", "smc_batch_destroy",
             "smc_batch_autotune", "smc_batch_waves", "smc_batch_init", "smc_batch_step",
@@ -305,6 +308,22 @@ def smc_resample_weights(lw_ptr, n, scheme, threshold, force, seed, step, proble
     _check(load().smc_resample_weights(_vp(lw_ptr), n, scheme, threshold, force, seed, step,
                                        problem, _vp(anc_ptr), _vp(summary_ptr), _vp(ws_ptr),
                                        ws_bytes, _vp(stream_handle)), "smc_resample_weights")
+
+
+NOALLOC_SCRATCH_BYTES = 4 << 20   # SMC_NOALLOC_SCRATCH_BYTES
+
+
+def smc_resample_weights_noalloc(lw_ptr, n, scheme, threshold, force, seed, step, problem,
+                                 anc_ptr, summary_ptr, stream_handle):
+    need = smc_resample_weights_workspace(n, scheme)
+    if need > NOALLOC_SCRATCH_BYTES:
+        raise SmcError(SMC_ERR_INVALID_ARG, "smc_resample_weights_noalloc",
+                       "n=%d needs %d bytes of workspace, more than the library's static %d"
+                       % (n, need, NOALLOC_SCRATCH_BYTES))
+    _check(load().smc_resample_weights_noalloc(_vp(lw_ptr), n, scheme, threshold, force, seed,
+                                               step, problem, _vp(anc_ptr), _vp(summary_ptr),
+                                               _vp(stream_handle)),
+           "smc_resample_weights_noalloc")
 
 
 def smc_profile_start(ctx, count):

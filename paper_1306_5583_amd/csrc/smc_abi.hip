@@ -5,6 +5,7 @@
 
 #include <new>
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "smc_internal.hpp"
@@ -763,6 +764,68 @@ smc_status smc_resample_weights(const double *lw, int64_t n, int32_t scheme, dou
         return s;
     return resample_weights_on(lw, n, scheme, threshold, force, seed, step, problem, ancestors,
                                summary, static_cast<char *>(workspace),
+                               static_cast<hipStream_t>(hip_stream));
+}
+
+}  // extern "C"
+
+namespace smc {
+
+// Workspace of smc_resample_weights_noalloc: one array per device, held
+// until the process ends.  Host code never passes `scratch` itself (on the
+// host it names a stand-in, not device memory): the device address comes
+// from hipGetSymbolAddress, taken once per device with that device current,
+// and kernels receive that address.
+static __device__ __align__(256) char scratch[SMC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static void *scratch_addr[MAX_DEVICES];
+
+static smc_status scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        (void)hipGetLastError();
+        return SMC_ERR_DEVICE;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return SMC_ERR_DEVICE;
+        }
+        scratch_addr[dev] = p;
+    }
+    *out = scratch_addr[dev];
+    return SMC_OK;
+}
+
+}  // namespace smc
+
+extern "C" {
+
+smc_status smc_resample_weights_noalloc(const double *lw, int64_t n, int32_t scheme,
+                                        double threshold, int32_t force, uint64_t seed,
+                                        uint32_t step, uint32_t problem, int32_t *ancestors,
+                                        double *summary, void *hip_stream)
+{
+    smc_status s = resample_weights_args(lw, n, scheme, ancestors, summary);
+    if (s != SMC_OK)
+        return s;
+    size_t sc;
+    if (plan_resample_workspace(n, scheme, &sc).total > SMC_NOALLOC_SCRATCH_BYTES)
+        return SMC_ERR_INVALID_ARG;
+    std::string err;
+    if ((s = device_ok(err)) != SMC_OK)
+        return s;
+    void *ws = nullptr;
+    if ((s = scratch_of_current_device(&ws)) != SMC_OK)
+        return s;
+    return resample_weights_on(lw, n, scheme, threshold, force, seed, step, problem, ancestors,
+                               summary, static_cast<char *>(ws),
                                static_cast<hipStream_t>(hip_stream));
 }
 

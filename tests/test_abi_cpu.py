@@ -186,6 +186,7 @@ def test_resample_weights_arguments(L):
     sys_b = L.smc_resample_weights_workspace(n, 1)
     mn_b = L.smc_resample_weights_workspace(n, 0)
     assert 0 < sys_b < 1 << 20 and mn_b >= sys_b + 8 * (n + 1)
+    assert L.smc_resample_weights_workspace(n, 1) <= L.NOALLOC_SCRATCH_BYTES < mn_b
     fake = 1 << 30        # aligned stand-in addresses, never dereferenced
     cases = [
         (0, n, 1, fake, fake, fake, sys_b),              # null log-weights
@@ -200,3 +201,10 @@ def test_resample_weights_arguments(L):
                                         None) == L.SMC_ERR_INVALID_ARG
     assert lib.smc_resample_weights(fake, n, 1, 0.5, 0, 1, 1, 0, fake, fake, fake, sys_b,
                                     None) == L.SMC_ERR_DEVICE
+    # the variant without a workspace: the static array's limit, then the device
+    assert lib.smc_resample_weights_noalloc(fake, n, 0, 0.5, 0, 1, 1, 0, fake, fake,
+                                            None) == L.SMC_ERR_INVALID_ARG
+    assert lib.smc_resample_weights_noalloc(0, n, 1, 0.5, 0, 1, 1, 0, fake, fake,
+                                            None) == L.SMC_ERR_INVALID_ARG
+    assert lib.smc_resample_weights_noalloc(fake, n, 1, 0.5, 0, 1, 1, 0, fake, fake,
+                                            None) == L.SMC_ERR_DEVICE
