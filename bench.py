@@ -67,8 +67,8 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1 << 20)
     ap.add_argument("--cpu-sample-T", type=int, default=30)
-    ap.add_argument("--variants", action="store_true",
-                    help="also time the FP32-state and multinomial variants")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="pf: skip the FP32-state and multinomial forms of the workload")
     ap.add_argument("--tune", action="store_true", help="batch: run the autotuner first")
     ap.add_argument("--model-seeds", type=int, default=4, help="models: seeds per K")
     ap.add_argument("--study-problem", default="c2", choices=["c2", "c3"])
@@ -111,9 +111,27 @@ def read_profile_values(fname):
 
 
 def _bytes_per_particle(fp32: bool, gathered: bool) -> int:
-    # state rows in + out, log-weight in + out, ancestor index when gathering
+    """Algorithmic bytes of the fused move + weight per particle: state rows
+    in and out, the new log-weight out, and either the old log-weight in or,
+    right after a resample (the old weights count as zero and are not read),
+    the ancestor index."""
     s = 4 if fp32 else 8
-    return 2 * 4 * s + 2 * 8 + (4 if gathered else 0)
+    return 2 * 4 * s + 8 + (4 if gathered else 8)
+
+
+RESAMPLE_BYTES = 12     # per particle when resampling fires: log-weight in, ancestor out
+# per 1024-particle tile and step: tile partial (32 B) and monitor partials
+# (40 B) written by the move and read by the normalisation, tile offsets of
+# the cumulative weights written (8 B) and read by the resampling (16 B)
+TILE_BYTES = 32 + 32 + 40 + 40 + 8 + 16
+
+
+def _step_bytes(n: int, fp32: bool, gathered: bool, resampled: bool) -> float:
+    """Algorithmic HBM bytes of one whole step of the sweep: move + weight,
+    normalisation, and the resampling when its decision fires."""
+    tiles = -(-n // 1024)
+    return (n * (_bytes_per_particle(fp32, gathered) + (RESAMPLE_BYTES if resampled else 0))
+            + tiles * TILE_BYTES)
 
 
 def copy_gbs(nbytes=1 << 30, reps=5):
@@ -140,11 +158,15 @@ def copy_gbs(nbytes=1 << 30, reps=5):
 # ------------------------------------------------------------ particle filter
 
 def run_pf(args, n, fp32, scheme, steps, warmup, timing=True):
+    """Times `steps` whole steps of the filter (wall clock, no events in the
+    stream), then, on a second filter of the same size, times the move
+    kernel of PROFILE_SAMPLE further steps by events carried in each
+    launch's own dispatch (separately, so they cannot slow the timed run)."""
     import torch
     import synth
     from paper_1306_5583_amd import ParticleFilter, _lib as L
 
-    T_needed = 1 + warmup + steps
+    T_needed = 1 + warmup + max(steps, PROFILE_SAMPLE)
     T = max(args.T, T_needed)
     _, y = synth.pf_trajectory(T, synth.DATA_SEED[1])
     # a throwaway run of the same filter first: the GPU leaves its idle clock
@@ -154,89 +176,158 @@ def run_pf(args, n, fp32, scheme, steps, warmup, timing=True):
     torch.cuda.synchronize()
     pfw.close()
     del pfw
-    pf = ParticleFilter(n, y, seed=1, scheme=scheme, fp32_state=fp32)
-    pf.init()
-    for t in range(1, 1 + warmup):
-        pf.step(t)
-    torch.cuda.synchronize()
-    m = pf._margs
-    sample = min(steps, PROFILE_SAMPLE)
-    if timing:
-        # the move kernels of the first `sample` timed steps carry their own
-        # start/stop events in their dispatch (no extra packets enter the
-        # stream); events on every launch would cost each step ~14 us of
-        # wall time, so only a sample is timed
-        L.smc_profile_start(pf.ctx, sample)
-    t0 = time.perf_counter()
-    for t in range(1 + warmup, 1 + warmup + steps):
+
+    def issue(pf, t):
         # fused move + weight; the same pass completes the previous step's monitor
+        m = pf._margs
         m.obs_index = t
         m.monitor_step = t - 1
         L.smc_move(pf.ctx, t, m)
         L.smc_ess(pf.ctx, t)
         L.smc_resample(pf.ctx, t)
+
+    pf = ParticleFilter(n, y, seed=1, scheme=scheme, fp32_state=fp32)
+    pf.init()
+    for t in range(1, 1 + warmup):
+        issue(pf, t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(1 + warmup, 1 + warmup + steps):
+        issue(pf, t)
     L.smc_monitor(pf.ctx, warmup + steps)   # the last step's monitor
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    move_ms = L.smc_profile_read(pf.ctx, sample) if timing else []
     pf.check()
     hist = pf.history_host()
     flags = hist[:, L.SMC_H_FLAG]
-    # algorithmic bytes of the timed launches (a gathered step reads the
-    # ancestor index too)
-    tot_bytes = 0.0
-    for t in range(1 + warmup, 1 + warmup + sample):
-        tot_bytes += n * _bytes_per_particle(fp32, bool(flags[t - 1]))
+    step_bytes = [_step_bytes(n, fp32, bool(flags[t - 1]), bool(flags[t]))
+                  for t in range(1 + warmup, 1 + warmup + steps)]
     res = {
         "wall_s": wall,
         "ms_per_step": 1e3 * wall / steps,
         "value": n * steps / wall,
-        "move_ms_avg": float(np.mean(move_ms)) if move_ms else None,
-        "move_bytes_avg": tot_bytes / max(sample, 1),
+        "step_bytes_avg": float(np.mean(step_bytes)),
         "resample_fraction": float(np.mean(flags[1 + warmup:1 + warmup + steps])),
         "log_z": float(hist[warmup + steps, L.SMC_H_LOGZ]),
     }
     pf.close()
     del pf
+    if timing:
+        pf = ParticleFilter(n, y, seed=1, scheme=scheme, fp32_state=fp32)
+        pf.init()
+        for t in range(1, 1 + warmup):
+            issue(pf, t)
+        sample = PROFILE_SAMPLE
+        L.smc_profile_start(pf.ctx, sample)
+        for t in range(1 + warmup, 1 + warmup + sample):
+            issue(pf, t)
+        torch.cuda.synchronize()
+        move_ms = L.smc_profile_read(pf.ctx, sample)
+        pf.check()
+        flags = pf.history_host()[:, L.SMC_H_FLAG]
+        res["move_ms_avg"] = float(np.mean(move_ms))
+        res["move_bytes_avg"] = float(np.mean(
+            [n * _bytes_per_particle(fp32, bool(flags[t - 1]))
+             for t in range(1 + warmup, 1 + warmup + sample)]))
+        pf.close()
+        del pf
     torch.cuda.empty_cache()
     return res
 
 
-def cpu_baseline_pf(args):
+def _cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def _host_threads():
+    """Threads for the all-core oracle timing: the CPU share of this process
+    (its affinity mask), at most 16 (a GPU machine's share per GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline_pf(args, fp32=False, scheme=None):
+    """The oracle on the machine's host, on bounded samples of the workload (the
+    first 30 observations): all the process's cores (up to 16) at the full
+    particle count, and one thread at N = 2^20.  The oracle runs its
+    per-particle loops on the threads and its sums sequentially, so both
+    give the results of the sequential oracle."""
     import oracle
     import synth
-    n, T = args.cpu_sample_n, args.cpu_sample_T
-    _, y = synth.pf_trajectory(T, synth.DATA_SEED[1])
-    cfg = oracle.pf_cfg(n, 1, scheme=args.scheme, fp32_state=args.fp32_state)
+    scheme = scheme or args.scheme
     oracle.build()
-    t0 = time.perf_counter()
-    oracle.pf_run(cfg, y)
-    wall = time.perf_counter() - t0
-    return {"value": n * (T - 1) / wall, "unit": METRIC, "cores": 1, "kind": "oracle",
-            "sample": "tracking filter, N=%d, %d observations (init + %d timed steps; the "
-                      "init is inside the wall), %s, single-threaded C oracle; wall %.2f s"
-                      % (n, T, T - 1, args.scheme, wall)}
+    out = {}
+    threads = _host_threads()
+    for label, th, n, T in (("one_thread", 1, args.cpu_sample_n, args.cpu_sample_T),
+                            ("all_cores", threads, args.n, args.cpu_sample_T)):
+        _, y = synth.pf_trajectory(T, synth.DATA_SEED[1])
+        cfg = oracle.pf_cfg(n, 1, scheme=scheme, fp32_state=fp32)
+        oracle.set_threads(th)
+        t0 = time.perf_counter()
+        oracle.pf_run(cfg, y)
+        wall = time.perf_counter() - t0
+        out[label] = {"value": n * (T - 1) / wall, "cores": th, "n": n, "T": T, "wall_s": wall}
+    oracle.set_threads(threads)
+    best = out["all_cores"]
+    res = {"value": best["value"], "unit": METRIC, "cores": best["cores"], "kind": "oracle",
+           "sample": "tracking filter at the full particle count, the first observations "
+                     "(N=%d, %d observations: init + %d steps, init inside the wall), %s%s, C "
+                     "oracle with its per-particle loops on %d threads (sums sequential); "
+                     "wall %.1f s"
+                     % (best["n"], best["T"], best["T"] - 1, scheme,
+                        ", fp32 state" if fp32 else "", best["cores"], best["wall_s"]),
+           "one_thread": dict(out["one_thread"], unit=METRIC,
+                              sample="N=%d, %d observations, 1 thread"
+                                     % (out["one_thread"]["n"], out["one_thread"]["T"]))}
+    res.update(_cpu_info())
+    return res
 
 
 def cpu_baseline_gmm(workload, K, nd, y, move):
     """The oracle's whole sampler (Algorithm 'gmm', same data, schedule and
-    move) on a bounded sample: fewer particles and the first steps of the
-    schedule (the work per step does not depend on alpha)."""
+    move) on bounded samples: fewer particles and the first steps of the
+    schedule (the work per step does not depend on alpha); one thread, and
+    all the process's cores (up to 16) on a sample four times as large."""
     import oracle
     import synth
     from paper_1306_5583_amd import mala_scales, rw_scales
-    n, Ts, T = (1 << 12, 25, 100) if workload == "gmm-c2" else (1 << 9, 10, 200)
+    n1, Ts, T = (1 << 12, 25, 100) if workload == "gmm-c2" else (1 << 9, 10, 200)
     alphas = synth.prior_tempering(T, 4.0)[:Ts + 1]
     f = rw_scales if move == "rw" else mala_scales
     scales = np.array([f(a) for a in alphas])
     oracle.build()
-    t0 = time.perf_counter()
-    oracle.gmm_run(oracle.gmm_cfg(n, 1, K, move=move), y, alphas, scales)
-    wall = time.perf_counter() - t0
-    return {"value": n * Ts / wall, "unit": METRIC, "cores": 1, "kind": "oracle",
-            "sample": "mixture sampler K=%d, n=%d data, N=%d, the first %d of %d steps "
-                      "(init inside the wall), %s moves, single-threaded C oracle; wall %.2f s"
-                      % (K, nd, n, Ts, T, move, wall)}
+    threads = _host_threads()
+    out = {}
+    for label, th, n in (("one_thread", 1, n1), ("all_cores", threads, 4 * n1)):
+        oracle.set_threads(th)
+        t0 = time.perf_counter()
+        oracle.gmm_run(oracle.gmm_cfg(n, 1, K, move=move), y, alphas, scales)
+        wall = time.perf_counter() - t0
+        out[label] = {"value": n * Ts / wall, "cores": th, "n": n, "steps": Ts, "wall_s": wall}
+    oracle.set_threads(threads)
+    best = out["all_cores"]
+    res = {"value": best["value"], "unit": METRIC, "cores": best["cores"], "kind": "oracle",
+           "sample": "mixture sampler K=%d, n=%d data, N=%d, the first %d of %d steps (init "
+                     "inside the wall), %s moves, C oracle with its per-particle loops on %d "
+                     "threads (sums sequential); wall %.2f s"
+                     % (K, nd, best["n"], Ts, T, move, best["cores"], best["wall_s"]),
+           "one_thread": dict(out["one_thread"], unit=METRIC,
+                              sample="N=%d, first %d steps, 1 thread"
+                                     % (out["one_thread"]["n"], Ts))}
+    res.update(_cpu_info())
+    return res
 
 
 def pf_traffic():
@@ -249,6 +340,18 @@ def pf_traffic():
     fetch = float(v["fetch_kib_per_launch"]) * 1024 / float(v["copy_fetch_factor"])
     write = float(v["write_kib_per_launch"]) * 1024 / float(v["copy_write_factor"])
     return fetch + write
+
+
+def _pf_label(fp32, scheme):
+    return "%s_%s" % ("fp32_state" if fp32 else "fp64", scheme)
+
+
+def _sweep(res):
+    """Whole-step HBM figures: algorithmic bytes of the step (move + weight,
+    normalisation, resampling when it fired) over the wall time per step."""
+    gbs = res["step_bytes_avg"] / (res["ms_per_step"] * 1e-3) / 1e9
+    return {"bytes_per_step": res["step_bytes_avg"], "achieved": gbs, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
 
 
 def bench_pf(args):
@@ -281,21 +384,35 @@ def bench_pf(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "pf_move_kernel (fused move + incremental log-weight)",
                      "avg_launch_ms": main_res["move_ms_avg"],
-                     "bytes_per_launch": main_res["move_bytes_avg"]},
+                     "bytes_per_launch": main_res["move_bytes_avg"],
+                     "timing": "events in the dispatch of %d move launches of a separate run "
+                               "after the timed steps" % PROFILE_SAMPLE},
+        "sweep_roofline": _sweep(main_res),
         "resample_fraction": main_res["resample_fraction"],
         "log_z": main_res["log_z"],
         "hbm_copy_gbs": copy_gbs(),
     }
-    if args.variants:
+    if not args.no_variants:
+        # the rest of the workload's four forms: {fp64, fp32 state} x
+        # {systematic, multinomial}
         var = {}
-        for name, fp32, scheme in [("fp32_state_systematic", True, "systematic"),
-                                   ("fp64_multinomial", False, "multinomial")]:
-            r = run_pf(args, n, fp32, scheme, min(args.steps, 60), 5)
-            var[name] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
-                         "move_gbs": r["move_bytes_avg"] / (r["move_ms_avg"] * 1e-3) / 1e9}
+        for fp32 in (False, True):
+            for scheme in ("systematic", "multinomial"):
+                if fp32 == args.fp32_state and scheme == args.scheme:
+                    continue
+                r = run_pf(args, n, fp32, scheme, min(args.steps, 60), 5)
+                mg = r["move_bytes_avg"] / (r["move_ms_avg"] * 1e-3) / 1e9
+                var[_pf_label(fp32, scheme)] = {
+                    "value": r["value"], "ms_per_step": r["ms_per_step"],
+                    "steps": min(args.steps, 60),
+                    "resample_fraction": r["resample_fraction"],
+                    "sweep_roofline": _sweep(r),
+                    "move_kernel": {"achieved": mg, "frac": mg / HBM_PEAK_GBS,
+                                    "avg_launch_ms": r["move_ms_avg"],
+                                    "bytes_per_launch": r["move_bytes_avg"]}}
         out["variants"] = var
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_pf(args)
+        out["cpu_baseline"] = cpu_baseline_pf(args, args.fp32_state, args.scheme)
     return out
 
 
@@ -375,17 +492,23 @@ def bench_gmm(args):
     warm.close()
     s = GmmSampler(n, y, K, T, seed=1, move=move)
     blocks = 3 if K > 1 else 2
-    # one Metropolis launch per step covers its `blocks` likelihood passes;
-    # the first PROFILE_SAMPLE launches carry timing events
-    sample = min(T, PROFILE_SAMPLE)
-    L.smc_profile_start(s.ctx, sample)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     logz = s.run(alphas)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    blk_ms = L.smc_profile_read(s.ctx, sample)
     s.check()
+    # one Metropolis launch per step covers its `blocks` likelihood passes;
+    # PROFILE_SAMPLE of them are timed by events in their own dispatch, in a
+    # separate run after the timed one
+    sample = min(T, PROFILE_SAMPLE)
+    p = GmmSampler(n, y, K, T, seed=3, move=move)
+    L.smc_profile_start(p.ctx, sample)
+    p.run(alphas[:sample + 1])
+    torch.cuda.synchronize()
+    blk_ms = L.smc_profile_read(p.ctx, sample)
+    p.check()
+    p.close()
     hist = s.history_host()
     terms_per_launch = n * nd * K * blocks
     avg_ms = float(np.mean(blk_ms))

@@ -30,8 +30,20 @@ def test_profile_values_parse():
 
 
 def test_algorithmic_bytes_per_particle():
-    # 4 state rows in and out plus the log-weight in and out; a gathered
-    # step adds the 4-byte ancestor index
+    # 4 state rows in and out plus the log-weight in and out; right after a
+    # resample the old log-weights count as zero and are not read, the
+    # 4-byte ancestor index is read instead
     assert bench._bytes_per_particle(False, False) == 80
-    assert bench._bytes_per_particle(False, True) == 84
+    assert bench._bytes_per_particle(False, True) == 76
     assert bench._bytes_per_particle(True, False) == 48
+    assert bench._bytes_per_particle(True, True) == 44
+
+
+def test_step_bytes():
+    # a whole step: the move, the resampling when it fires (log-weight in,
+    # ancestor out: 12 B per particle) and per-tile partials
+    n = 1 << 22
+    tiles = n // 1024
+    assert bench._step_bytes(n, False, True, True) == n * (76 + 12) + tiles * bench.TILE_BYTES
+    assert bench._step_bytes(n, False, False, False) == n * 80 + tiles * bench.TILE_BYTES
+    assert bench._step_bytes(1000, True, False, True) == 1000 * (48 + 12) + bench.TILE_BYTES
