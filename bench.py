@@ -554,10 +554,8 @@ def bench_batch(args):
     specs = [pkg.PfSpec(**kw) if k == "pf" else pkg.GmmSpec(move="mala", **kw)
              for k, kw in work]
     br = pkg.BatchRunner(specs)
-    Ks = sorted({kw["K"] for k, kw in work if k == "gmm"})
     if args.tune:
-        br.autotune(5, None)
-    waves = {K: br.waves(K) for K in Ks}
+        br.autotune(3, None)
     br.run(3, graph=True)          # warm-up (graph capture included)
     br.check()
     torch.cuda.synchronize()
@@ -574,12 +572,12 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {"workload": "batched: 128 tracking filters (N log-uniform in [2^10, 2^18]) "
                                "+ 32 MALA mixture samplers (K in 2..8, n log-uniform in "
-                               "[500, 20000], N log-uniform in [2^12, 2^16]), 200 steps, one "
-                               "HIP graph per step", "problems": len(work),
-                   "particles": parts},
+                               "[500, 20000], N log-uniform in [2^12, 2^16]), 200 steps, each "
+                               "step one persistent launch (captured in a HIP graph)",
+                   "problems": len(work), "particles": parts},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
-        "waves_per_tile": {str(k): v for k, v in waves.items()},
+        "schedule": br.schedule(),
         "tuned": bool(args.tune),
     }
     br.close()
@@ -592,7 +590,7 @@ def bench_models(args):
     """Bayesian model comparison over the number of mixture components
     (Section 5.2: the evidence p(y | M_r) of every r = 1..8 on the
     four-component data of the random-walk sampler, several seeds each),
-    all samplers advanced together as one batched HIP graph per step.
+    all samplers advanced together, one persistent launch per step.
     Posterior model probabilities assume a uniform prior over r."""
     import torch
     import synth
@@ -625,7 +623,7 @@ def bench_models(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "model comparison: random-walk mixture samplers for K=1..8 "
                                "(x%d seeds), n=1000 four-component data, N=2^14 each, T=100, "
-                               "alpha=(t/T)^4, one batched HIP graph per step" % len(seeds),
+                               "alpha=(t/T)^4, one persistent launch per step" % len(seeds),
                    "K": Ks, "seeds": len(seeds), "n": n, "T": T},
         "log_z": {str(K): float(m) for K, m in zip(Ks, mean)},
         "log_z_se": {str(K): float(e) for K, e in zip(Ks, se)},

@@ -123,7 +123,8 @@ enum {
 enum {
     SMC_DEVERR_ZERO_WEIGHTS = 1, /* all weights zero / total not finite at a resample */
     SMC_DEVERR_NONFINITE = 2,    /* NaN log-weight total at a normalisation */
-    SMC_DEVERR_GAMMA = 4         /* gamma sampler exhausted its attempts */
+    SMC_DEVERR_GAMMA = 4,        /* gamma sampler exhausted its attempts */
+    SMC_DEVERR_TIMEOUT = 8       /* batched step: a wait for other work items timed out */
 };
 
 typedef struct smc_config {
@@ -357,21 +358,27 @@ smc_status smc_profile_start(smc_ctx *ctx, int32_t count);
 smc_status smc_profile_read(smc_ctx *ctx, float *ms, int32_t capacity, int32_t *written);
 
 /* ------------------------------------------------------------------------
- * Batched form: many independent filters and samplers of different sizes
- * advanced together.  Each phase of a step (move / reweight, normalisation,
- * resampling, each Metropolis block) is ONE launch covering every problem's
- * tiles, the step index lives on the device, and a step can be captured
- * once into a HIP graph and replayed.  Every problem computes exactly what
- * its own single-problem context would (same kernels, same Philox counters
- * with its problem_id); the batch only changes how the work is launched.
- * Restrictions: systematic resampling, double-precision tracking state,
- * the same move kind and sweep count for all mixture samplers.
+ * Batched form (the paper's two examples, many problems at once): many
+ * independent filters and samplers of different sizes advanced together,
+ * each step ONE launch of a persistent kernel whose workgroups take work
+ * items -- (problem, phase, tile): move / reweight tiles, normalisations,
+ * resampling tiles, Metropolis tiles -- from a queue in ticket order,
+ * waiting on per-problem completion counters for the items each depends
+ * on.  The queue lists every item after the items it waits for, so the
+ * step progresses whatever the number of co-resident workgroups; waits are
+ * bounded (a time-out raises SMC_DEVERR_TIMEOUT and the rest of the step is
+ * skipped).  A step can be captured once into a HIP graph and replayed.
+ * Every problem computes exactly what its own single-problem context would
+ * (same per-tile functions, same Philox counters with its problem_id); the
+ * batch only changes how the work is scheduled.  Supported: systematic and
+ * stratified resampling, FP64 or FP32 tracking state, mixture samplers with
+ * up to BATCH_MAX_K = 8 components, any mix of move kinds and sweep counts.
  * ------------------------------------------------------------------------ */
 typedef struct smc_batch smc_batch;
 
 typedef struct smc_batch_problem {
-    smc_config cfg;          /* as for smc_create (scheme must be systematic; a tracking
-                                filter must have precision SMC_F64) */
+    smc_config cfg;          /* as for smc_create (systematic or stratified resampling;
+                                mixture samplers with K <= 8) */
     smc_buffers buf;         /* the problem's own device buffers, as for smc_create; the
                                 state of step t lives in state (t even) or state_alt
                                 (t odd) */
@@ -381,48 +388,77 @@ typedef struct smc_batch_problem {
     int32_t schedule_len;    /* mixture samplers: rows of schedule (steps + 1) */
 } smc_batch_problem;
 
-/* Device bytes of the batch table (problem descriptors, tile maps, step
- * counter) the caller must provide to smc_batch_create.  Validates every
- * configuration (SMC_ERR_INVALID_ARG as smc_create would). */
+/* Device bytes of the batch table (problem descriptors, tile maps, the work
+ * queue, completion counters) the caller must provide to smc_batch_create.
+ * Validates every configuration (SMC_ERR_INVALID_ARG as smc_create would;
+ * SMC_ERR_UNSUPPORTED for multinomial resampling or K > 8). */
 smc_status smc_batch_table_size(const smc_batch_problem *probs, int32_t nprob, size_t *bytes);
+/* The work queue of one step for these problems, without any device work
+ * (for inspection and host-side checks of the schedule): order 0 = the
+ * mixture samplers' reweight / normalise / resample items, their Metropolis
+ * tiles with the most expensive problems first, then the tracking filters'
+ * items; order 1 = phase by phase in problem order.  per_item (1 or 2)
+ * 64-particle tiles make one Metropolis item.  items receives *count rows of
+ * four int32 {kind (0 move, 1 reweight, 2 normalise, 3 resample, 4
+ * Metropolis), problem, tile, tiles in the item}; with capacity 0 only
+ * *count is written.  SMC_ERR_INVALID_ARG when capacity is non-zero and too
+ * small. */
+smc_status smc_batch_plan_queue(const smc_batch_problem *probs, int32_t nprob, int32_t order,
+                                int32_t per_item, int32_t *items, int64_t capacity,
+                                int64_t *count);
 /* Builds the batch over caller-owned memory: `table` (device, 256-byte
  * aligned, at least smc_batch_table_size bytes) and every problem's buffers
  * must outlive the batch; all work is enqueued on `hip_stream`, which must
- * not be the legacy null stream when steps are captured.  Errors:
- * SMC_ERR_INVALID_ARG (null or misaligned arguments, a configuration or
- * buffer set smc_create would refuse, a mixture sampler without a
- * schedule, a table that is too small), SMC_ERR_UNSUPPORTED (another
- * resampling scheme, FP32 tracking state, mixture samplers with different
- * move kinds or sweep counts), SMC_ERR_DEVICE (not a gfx950 device, or a
- * copy failed).  Nothing is created on error. */
+ * not be the legacy null stream when steps are captured.  The step launch
+ * starts as many workgroups as the device holds at once (occupancy x
+ * compute units) with queue order 0 and one tile per Metropolis item.
+ * Errors: SMC_ERR_INVALID_ARG (null or misaligned arguments, a
+ * configuration or buffer set smc_create would refuse, a mixture sampler
+ * without a schedule, a table that is too small), SMC_ERR_UNSUPPORTED
+ * (multinomial resampling, K > 8), SMC_ERR_DEVICE (not a gfx950 device, or
+ * a copy failed).  Nothing is created on error. */
 smc_status smc_batch_create(const smc_batch_problem *probs, int32_t nprob, void *table,
                             size_t table_bytes, void *hip_stream, smc_batch **out);
 /* Releases the host object and its captured graph (not the caller's memory). */
 smc_status smc_batch_destroy(smc_batch *b);
-/* Picks the waves per 64-particle tile of every mixture-size group by timing
- * the prior-draw + likelihood kernel on the batch's own shapes (`repeats`
- * launches per candidate 1, 2, 4, 8, median kept); reads / extends a text
- * cache of lines "<arch> K=<K> log2n=<l> log2nd=<m> W=<w>" when cache_path
- * is non-NULL.  Synchronises the stream.  Leaves the state undefined and
- * drops a captured graph: call smc_batch_init (and capture again)
- * afterwards. */
+/* Autotuner of the step: for every candidate schedule -- queue order (0, 1),
+ * 64-particle tiles per Metropolis item (1, 2), step workgroups per compute
+ * unit (1 .. the occupancy limit) -- initialises the batch and times
+ * `repeats` steps after a warm-up step (median kept), then keeps the
+ * fastest.  With a non-NULL cache_path, a line "<arch> <shape buckets> |
+ * order=o per_item=q wgs_per_cu=w step_ms=..." (shape buckets: per problem
+ * type, mixture size and move kind, the rounded-up log2 of the particle and
+ * data counts, with their multiplicities) is read instead of measuring when
+ * present, and appended after measuring.  Synchronises the stream.  Leaves
+ * the state undefined and drops a captured graph: call smc_batch_init (and
+ * capture again) afterwards. */
 smc_status smc_batch_autotune(smc_batch *b, int32_t repeats, const char *cache_path);
-/* Waves per tile chosen for the mixture samplers with K components
- * (SMC_ERR_INVALID_ARG when the batch has none). */
+/* The step's schedule: out[5] = {queue order, tiles per Metropolis item,
+ * workgroups per compute unit, workgroups of the launch, items per step}. */
+smc_status smc_batch_schedule(const smc_batch *b, int32_t *out);
+/* Sets the step's schedule without measuring: queue order (0, 1), tiles per
+ * Metropolis item (1, 2), workgroups per compute unit (clamped to the
+ * occupancy limit).  Results do not depend on the schedule.  Copies the new
+ * queue to the device (synchronously) and drops a captured graph; not to be
+ * called while the stream is being captured. */
+smc_status smc_batch_set_schedule(smc_batch *b, int32_t order, int32_t per_item,
+                                  int32_t wgs_per_cu);
+/* Waves per 64-particle tile of the initialisation of the mixture samplers
+ * with K components (SMC_ERR_INVALID_ARG when the batch has none). */
 smc_status smc_batch_waves(const smc_batch *b, int32_t K, int32_t *waves);
 /* Initialisation of every problem (as smc_init, then the t = 0
- * normalisation and resampling decision); device step counter = 0. */
+ * normalisation and resampling decision); resets the step's queue tickets
+ * and completion counters. */
 smc_status smc_batch_init(smc_batch *b);
-/* Enqueues one step of every problem (step index = device counter + 1):
- * tracking filters move + weight (completing the previous step's monitor),
- * mixture samplers reweight; all normalise and resample if their ESS is low;
- * mixture samplers then run their Metropolis blocks.  SMC_ERR_BAD_STATE
- * before smc_batch_init or when a problem has no observation / schedule /
- * history row left. */
+/* Enqueues one step of every problem (the step index follows from the
+ * tickets the launch consumes): tracking filters move + weight (completing
+ * the previous step's monitor), mixture samplers reweight; all normalise
+ * and resample if their ESS is low; mixture samplers then run their
+ * Metropolis blocks.  SMC_ERR_BAD_STATE before smc_batch_init or when a
+ * problem has no observation / schedule / history row left. */
 smc_status smc_batch_step(smc_batch *b);
 /* Captures one step into a HIP graph (replaces a previous capture); the
- * graph reads the step index from the device, so one capture serves every
- * step. */
+ * step index comes from the device, so one capture serves every step. */
 smc_status smc_batch_capture(smc_batch *b);
 /* Launches the captured step (same checks as smc_batch_step). */
 smc_status smc_batch_replay(smc_batch *b);

@@ -132,6 +132,10 @@ def load() -> ctypes.CDLL:
         "smc_batch_create": (st, [P(smc_batch_problem), _i32, _vp, ctypes.c_size_t, _vp,
                                   P(_vp)]),
         "smc_batch_destroy": (st, [_vp]),
+        "smc_batch_plan_queue": (st, [P(smc_batch_problem), _i32, _i32, _i32, _vp, _i64,
+                                      P(_i64)]),
+        "smc_batch_schedule": (st, [_vp, P(_i32)]),
+        "smc_batch_set_schedule": (st, [_vp, _i32, _i32, _i32]),
         "smc_batch_autotune": (st, [_vp, _i32, ctypes.c_char_p]),
         "smc_batch_waves": (st, [_vp, _i32, P(_i32)]),
         "smc_batch_init": (st, [_vp]),
@@ -158,6 +162,7 @@ def exported_symbols():
             "smc_resample_weights_noalloc",
             "smc_profile_start", "smc_profile_read", "smc_batch_table_size",
             "smc_batch_create", "smc_batch_destroy",
+            "smc_batch_plan_queue", "smc_batch_schedule", "smc_batch_set_schedule",
             "smc_batch_autotune", "smc_batch_waves", "smc_batch_init", "smc_batch_step",
             "smc_batch_capture", "smc_batch_replay", "smc_batch_check", "smc_batch_last_error"]
 
@@ -363,6 +368,33 @@ def smc_batch_create(probs, table_ptr, table_bytes, stream_handle):
 
 def smc_batch_destroy(b):
     _check(load().smc_batch_destroy(b), "smc_batch_destroy")
+
+
+def smc_batch_plan_queue(probs, order, per_item):
+    """The step's work queue for these problems (no device work): an int32
+    array [items][4] = kind, problem, tile, tiles in the item."""
+    import numpy as np
+    arr = _problem_array(probs)
+    cnt = _i64()
+    _check(load().smc_batch_plan_queue(arr, len(probs), order, per_item, None, 0,
+                                       ctypes.byref(cnt)), "smc_batch_plan_queue")
+    out = np.zeros((cnt.value, 4), dtype=np.int32)
+    _check(load().smc_batch_plan_queue(arr, len(probs), order, per_item,
+                                       out.ctypes.data_as(_vp), cnt.value, ctypes.byref(cnt)),
+           "smc_batch_plan_queue")
+    return out
+
+
+def smc_batch_schedule(b):
+    out = (_i32 * 5)()
+    _check(load().smc_batch_schedule(b, out), "smc_batch_schedule", batch=b)
+    return {"order": out[0], "per_item": out[1], "wgs_per_cu": out[2], "workgroups": out[3],
+            "items": out[4]}
+
+
+def smc_batch_set_schedule(b, order, per_item, wgs_per_cu):
+    _check(load().smc_batch_set_schedule(b, order, per_item, wgs_per_cu),
+           "smc_batch_set_schedule", batch=b)
 
 
 def smc_batch_autotune(b, repeats, cache_path=None):

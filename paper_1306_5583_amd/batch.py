@@ -1,8 +1,8 @@
 """Batched driver: many independent filters and samplers of uneven sizes
-advanced together through the smc_batch_* entry points (one launch per
-phase over every problem's tiles, the step counter on the device, one step
-capturable as a HIP graph).  Host logic only; every numeric step is a HIP
-kernel behind include/smc.h.
+advanced together through the smc_batch_* entry points (each step one
+launch of a persistent kernel that works through a dependency-ordered queue
+of (problem, phase, tile) items; one step capturable as a HIP graph).  Host
+logic only; every numeric step is a HIP kernel behind include/smc.h.
 
 Each problem is the single-problem algorithm of its kind (Section 5.1's
 filter, Section 5.2's tempered sampler) with its own seed and problem id in
@@ -31,6 +31,8 @@ class PfSpec:
     problem_id: int = 0
     threshold: float = 0.5
     obs_nu: float = 10.0
+    fp32_state: bool = False
+    scheme: str = "systematic"
 
 
 @dataclasses.dataclass
@@ -49,6 +51,7 @@ class GmmSpec:
     problem_id: int = 0
     threshold: float = 0.5
     prior: tuple = (0.0, 10.0, 1.0, 1.0, 1.0)
+    scheme: str = "systematic"
 
 
 def gmm_schedule(alphas, scales, move):
@@ -78,7 +81,8 @@ class BatchRunner:
                 T = int(y.shape[0])
                 cfg = L.make_config(L.SMC_MODEL_CV_TRACK, sp.n, seed=sp.seed,
                                     problem_id=sp.problem_id, threshold=sp.threshold,
-                                    obs_nu=sp.obs_nu, n_obs=T)
+                                    obs_nu=sp.obs_nu, n_obs=T, scheme=sp.scheme,
+                                    precision=L.SMC_F32_STATE if sp.fp32_state else L.SMC_F64)
                 buf = ProblemBuffers(cfg, y, T, self.device)
                 self.schedules.append(None)
                 bp.schedule = None
@@ -90,6 +94,7 @@ class BatchRunner:
                 S = int(sched.shape[0]) - 1
                 cfg = L.make_config(L.SMC_MODEL_GMM_TEMPERED, sp.n, seed=sp.seed,
                                     problem_id=sp.problem_id, threshold=sp.threshold, K=sp.K,
+                                    scheme=sp.scheme,
                                     n_data=int(y.numel()), prior=sp.prior,
                                     move_kind=L.SMC_MOVE_MALA if sp.move == "mala"
                                     else L.SMC_MOVE_RW, sweeps=sp.sweeps)
@@ -129,6 +134,18 @@ class BatchRunner:
 
     def waves(self, K: int) -> int:
         return L.smc_batch_waves(self.handle, K)
+
+    def schedule(self) -> dict:
+        """The step launch's schedule: queue order, tiles per Metropolis
+        item, workgroups (per compute unit and in all), items per step."""
+        return L.smc_batch_schedule(self.handle)
+
+    def set_schedule(self, order: int, per_item: int, wgs_per_cu: int):
+        L.smc_batch_set_schedule(self.handle, order, per_item, wgs_per_cu)
+
+    def queue(self, order: int = 0, per_item: int = 1) -> np.ndarray:
+        """The step's work queue for these problems (host only)."""
+        return L.smc_batch_plan_queue(self._probs, order, per_item)
 
     def init(self):
         L.smc_batch_init(self.handle)

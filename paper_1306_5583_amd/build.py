@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsmc.so")
 SOURCES = ["smc_abi.hip", "smc_core.hip", "smc_pf.hip", "smc_gmm.hip", "smc_gmm_ka.hip",
-           "smc_gmm_kb.hip", "smc_gmm_kc.hip", "smc_gmm_kd.hip", "smc_batch.hip"]
+           "smc_gmm_kb.hip", "smc_gmm_kc.hip", "smc_gmm_kd.hip", "smc_batch.hip",
+           "smc_persist.hip"]
 ARCH = "gfx950"
 
 

@@ -99,6 +99,8 @@ Prob prob_from(const smc_config &cfg, const smc_buffers &buf, const Workspace &w
     Prob P{};
     P.kind = cfg.model;
     P.move_kind = cfg.move_kind;
+    P.elem_bytes = (cfg.model == SMC_MODEL_CV_TRACK && cfg.precision == SMC_F32_STATE) ? 4 : 8;
+    P.sweeps = cfg.sweeps > 0 ? cfg.sweeps : 1;
     P.n = cfg.n;
     P.n_data = cfg.model == SMC_MODEL_CV_TRACK ? (int64_t)cfg.n_obs : cfg.n_data;
     P.ntiles = ceil_div(cfg.n, TILE);

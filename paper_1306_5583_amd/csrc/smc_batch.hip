@@ -13,11 +13,14 @@
 #include <vector>
 
 #include "smc_internal.hpp"
+#include "smc_batch_queue.hpp"
 
 namespace smc {
 
+// Problems of one mixture size and move kind, initialised by one launch.
 struct KGroup {
     int K = 0;
+    bool mala = false;
     int2 *map64 = nullptr;
     int64_t tiles64 = 0;
     int W = 1;
@@ -32,15 +35,23 @@ using namespace smc;
 struct smc_batch {
     std::vector<smc_batch_problem> probs;
     std::vector<Prob> P;
+    std::vector<QProblem> qp;
     hipStream_t stream = nullptr;
     char *table = nullptr;
     Prob *dprobs = nullptr;
     int2 *map_pf = nullptr, *map_gmm = nullptr, *map_all = nullptr;
     int64_t pf_tiles = 0, gmm_tiles = 0, all_tiles = 0;
     std::vector<KGroup> groups;
-    int32_t *step = nullptr;
-    bool mala = false;
-    int sweeps = 1;
+    int32_t *step = nullptr;        // step index of the initialisation kernels
+    QItem *queue = nullptr;         // one step's work items
+    int64_t queue_cap = 0;
+    uint32_t nitems = 0;
+    uint32_t *deps = nullptr;       // per-problem completion counters
+    uint32_t *sync = nullptr;       // ticket counter, abort flag
+    int cus = 0;                    // compute units of the device
+    int max_wgs_per_cu = 0;         // co-resident step workgroups per CU
+    int32_t order = ORDER_COST_FIRST, per_item = 1, wgs_per_cu = 0;
+    uint32_t nwg = 0;               // workgroups of the step launch
     bool initialised = false;
     int host_step = 0;
     int max_steps = 0;
@@ -52,11 +63,12 @@ struct smc_batch {
 namespace {
 
 struct Plan {
-    size_t probs = 0, map_pf = 0, map_gmm = 0, map_all = 0, step = 0, total = 0;
+    size_t probs = 0, map_pf = 0, map_gmm = 0, map_all = 0, step = 0, queue = 0, deps = 0,
+           sync = 0, total = 0;
     std::vector<size_t> map64;
-    std::vector<int> ks;
+    std::vector<std::pair<int, bool>> keys;  // (K, mala) of each mixture group
     std::vector<int64_t> tiles64;
-    int64_t pf_tiles = 0, gmm_tiles = 0;
+    int64_t pf_tiles = 0, gmm_tiles = 0, queue_cap = 0;
 };
 
 size_t al(size_t v) { return (v + 255) & ~size_t(255); }
@@ -64,15 +76,17 @@ size_t al(size_t v) { return (v + 255) & ~size_t(255); }
 Plan plan(const smc_batch_problem *probs, int32_t np)
 {
     Plan pl;
-    std::map<int, int64_t> t64;
+    std::map<std::pair<int, bool>, int64_t> t64;
     for (int32_t i = 0; i < np; ++i) {
         const smc_config &c = probs[i].cfg;
         const int64_t nt = ceil_div(c.n, TILE);
-        if (c.model == SMC_MODEL_CV_TRACK)
+        if (c.model == SMC_MODEL_CV_TRACK) {
             pl.pf_tiles += nt;
-        else {
+            pl.queue_cap += 2 * nt + 1;
+        } else {
             pl.gmm_tiles += nt;
-            t64[c.K] += ceil_div(c.n, WAVE);
+            t64[{c.K, c.move_kind == SMC_MOVE_MALA}] += ceil_div(c.n, WAVE);
+            pl.queue_cap += 2 * nt + 1 + ceil_div(c.n, WAVE);
         }
     }
     size_t off = 0;
@@ -85,15 +99,41 @@ Plan plan(const smc_batch_problem *probs, int32_t np)
     pl.map_all = off;
     off = al(off + sizeof(int2) * (size_t)(pl.pf_tiles + pl.gmm_tiles));
     for (auto &kv : t64) {
-        pl.ks.push_back(kv.first);
+        pl.keys.push_back(kv.first);
         pl.tiles64.push_back(kv.second);
         pl.map64.push_back(off);
         off = al(off + sizeof(int2) * (size_t)kv.second);
     }
     pl.step = off;
     off = al(off + 256);
+    pl.queue = off;
+    off = al(off + sizeof(QItem) * (size_t)pl.queue_cap);
+    pl.deps = off;
+    off = al(off + sizeof(uint32_t) * DEP_STRIDE * (size_t)np);
+    pl.sync = off;
+    off = al(off + sizeof(uint32_t) * SYNC_WORDS);
     pl.total = off;
     return pl;
+}
+
+// What the queue needs to know of each problem: its tiles and the relative
+// cost of one Metropolis tile (data points x components, MALA's gradient
+// and the sweeps).
+std::vector<QProblem> queue_problems(const smc_batch_problem *probs, int32_t np)
+{
+    std::vector<QProblem> q;
+    for (int32_t i = 0; i < np; ++i) {
+        const smc_config &c = probs[i].cfg;
+        QProblem r;
+        r.gmm = c.model == SMC_MODEL_GMM_TEMPERED;
+        r.tiles = ceil_div(c.n, TILE);
+        r.tiles64 = r.gmm ? ceil_div(c.n, WAVE) : 0;
+        r.cost = r.gmm ? (double)c.n_data * c.K * (c.move_kind == SMC_MOVE_MALA ? 1.4 : 1.0) *
+                             (c.sweeps > 0 ? c.sweeps : 1)
+                       : 0.0;
+        q.push_back(r);
+    }
+    return q;
 }
 
 smc_status bfail(smc_batch *b, smc_status s, const std::string &m)
@@ -110,45 +150,79 @@ smc_status bhip(smc_batch *b, hipError_t e, const char *where)
     return SMC_ERR_DEVICE;
 }
 
-hipError_t enqueue_step(smc_batch *b)
+// Validation shared by the table size, the queue inspection and creation.
+smc_status check_problem(const smc_batch_problem &q, std::string &err)
 {
-    hipStream_t s = b->stream;
-    hipError_t e = launch_set_step(b->step, 1, 1, s);
-    if (e == hipSuccess)
-        e = launch_pf_move_batch(b->dprobs, b->map_pf, b->pf_tiles, b->step, s);
-    if (e == hipSuccess)
-        e = launch_gmm_reweight_batch(b->dprobs, b->map_gmm, b->gmm_tiles, b->step, s);
-    if (e == hipSuccess)
-        e = launch_finalize_batch(b->dprobs, (int32_t)b->P.size(), b->step, s);
-    if (e == hipSuccess)
-        e = launch_resample_batch(b->dprobs, b->map_all, b->all_tiles, b->step, s);
-    for (int sw = 0; sw < b->sweeps && e == hipSuccess; ++sw)
-        for (int blk = 0; blk < 3 && e == hipSuccess; ++blk)
-            for (const KGroup &g : b->groups) {
-                if (blk == 2 && g.K == 1)
-                    continue;
-                const int first = (sw == 0 && blk == 0) ? 1 : 0;
-                e = launch_gmm_block_batch(b->dprobs, g.map64, g.tiles64, g.K, b->step, g.W, blk,
-                                           sw, first, b->mala, s);
-                if (e != hipSuccess)
-                    break;
-            }
-    return e;
+    smc_status s = validate_config(&q.cfg, err);
+    if (s != SMC_OK)
+        return s;
+    if (q.cfg.scheme != SMC_RS_SYSTEMATIC && q.cfg.scheme != SMC_RS_STRATIFIED)
+        return SMC_ERR_UNSUPPORTED;
+    if (q.cfg.model == SMC_MODEL_GMM_TEMPERED && q.cfg.K > BATCH_MAX_K)
+        return SMC_ERR_UNSUPPORTED;
+    return SMC_OK;
 }
 
-std::string cache_key(const KGroup &g)
+// Builds and uploads the step's queue for a schedule choice (not while a
+// step is captured: it copies from the host).
+hipError_t set_schedule(smc_batch *b, int32_t order, int32_t per_item, int32_t wgs_per_cu)
+{
+    const std::vector<QItem> q = build_queue(b->qp, order, per_item);
+    if ((int64_t)q.size() > b->queue_cap)
+        return hipErrorInvalidValue;
+    // steps already enqueued read the old queue
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->queue, q.data(), sizeof(QItem) * q.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return e;
+    b->order = order;
+    b->per_item = per_item;
+    b->wgs_per_cu = std::max(1, std::min(wgs_per_cu, b->max_wgs_per_cu));
+    b->nitems = (uint32_t)q.size();
+    b->nwg = (uint32_t)(b->wgs_per_cu * b->cus);
+    if (b->exec) {  // a captured step used the old schedule
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return hipSuccess;
+}
+
+// One step: a single launch of the persistent step kernel.
+hipError_t enqueue_step(smc_batch *b)
+{
+    return launch_batch_step(b->dprobs, b->queue, b->nitems, b->nwg, b->sync, b->deps,
+                             b->stream);
+}
+
+std::string cache_key(const smc_batch *b)
 {
     int dev = 0;
     hipDeviceProp_t prop;
     (void)hipGetDevice(&dev);
     (void)hipGetDeviceProperties(&prop, dev);
-    char buf[256];
-    snprintf(buf, sizeof(buf), "%s K=%d log2n=%d log2nd=%d", prop.gcnArchName, g.K,
-             (int)ceil(log2((double)std::max<int64_t>(g.sum_n, 1))),
-             (int)ceil(log2((double)std::max<int64_t>(g.max_nd, 1))));
-    std::string k(buf);
-    std::replace(k.begin(), k.end(), ':', '_');
-    return k;
+    // shape bucket: per problem type and mixture size, the problem count and
+    // the rounded-up log2 of the particles and of the data points
+    std::map<std::string, int> buckets;
+    for (const smc_batch_problem &q : b->probs) {
+        const smc_config &c = q.cfg;
+        char k[96];
+        if (c.model == SMC_MODEL_CV_TRACK)
+            snprintf(k, sizeof(k), "pf%d", (int)ceil(log2((double)c.n)));
+        else
+            snprintf(k, sizeof(k), "g%d%c%d.%d", c.K, c.move_kind == SMC_MOVE_MALA ? 'm' : 'r',
+                     (int)ceil(log2((double)c.n)), (int)ceil(log2((double)c.n_data)));
+        buckets[k] += 1;
+    }
+    std::string key = prop.gcnArchName;
+    for (auto &kv : buckets)
+        key += " " + kv.first + "x" + std::to_string(kv.second);
+    std::replace(key.begin(), key.end(), ':', '_');
+    return key;
 }
 
 }  // namespace
@@ -161,11 +235,37 @@ smc_status smc_batch_table_size(const smc_batch_problem *probs, int32_t nprob, s
         return SMC_ERR_INVALID_ARG;
     std::string err;
     for (int32_t i = 0; i < nprob; ++i) {
-        const smc_status s = validate_config(&probs[i].cfg, err);
+        const smc_status s = check_problem(probs[i], err);
         if (s != SMC_OK)
             return s;
     }
     *bytes = plan(probs, nprob).total;
+    return SMC_OK;
+}
+
+smc_status smc_batch_plan_queue(const smc_batch_problem *probs, int32_t nprob, int32_t order,
+                                int32_t per_item, int32_t *items, int64_t capacity,
+                                int64_t *count)
+{
+    if (!probs || nprob < 1 || !count || (order != ORDER_COST_FIRST && order != ORDER_PHASES) ||
+        per_item < 1 || per_item > 2 || capacity < 0 || (capacity > 0 && !items))
+        return SMC_ERR_INVALID_ARG;
+    std::string err;
+    for (int32_t i = 0; i < nprob; ++i) {
+        const smc_status s = check_problem(probs[i], err);
+        if (s != SMC_OK)
+            return s;
+    }
+    const std::vector<QItem> q = build_queue(queue_problems(probs, nprob), order, per_item);
+    *count = (int64_t)q.size();
+    if (capacity < (int64_t)q.size())
+        return capacity == 0 ? SMC_OK : SMC_ERR_INVALID_ARG;
+    for (size_t k = 0; k < q.size(); ++k) {
+        items[4 * k] = q[k].kind;
+        items[4 * k + 1] = q[k].prob;
+        items[4 * k + 2] = q[k].tile;
+        items[4 * k + 3] = q[k].count;
+    }
     return SMC_OK;
 }
 
@@ -178,28 +278,16 @@ smc_status smc_batch_create(const smc_batch_problem *probs, int32_t nprob, void 
     if (!probs || nprob < 1 || !table || (reinterpret_cast<uintptr_t>(table) % 256) != 0)
         return SMC_ERR_INVALID_ARG;
     std::string err;
-    int gmm_kind = -1, gmm_sweeps = -1;
     for (int32_t i = 0; i < nprob; ++i) {
         const smc_batch_problem &q = probs[i];
-        smc_status s = validate_config(&q.cfg, err);
+        smc_status s = check_problem(q, err);
         if (s != SMC_OK)
             return s;
         s = validate_buffers(q.cfg, &q.buf, err);
         if (s != SMC_OK)
             return s;
-        if (q.cfg.scheme != SMC_RS_SYSTEMATIC)
-            return SMC_ERR_UNSUPPORTED;
-        if (q.cfg.model == SMC_MODEL_CV_TRACK && q.cfg.precision != SMC_F64)
-            return SMC_ERR_UNSUPPORTED;
-        if (q.cfg.model == SMC_MODEL_GMM_TEMPERED) {
-            if (!q.schedule || q.schedule_len < 2)
-                return SMC_ERR_INVALID_ARG;
-            const int sw = q.cfg.sweeps > 0 ? q.cfg.sweeps : 1;
-            if (gmm_kind >= 0 && (gmm_kind != q.cfg.move_kind || gmm_sweeps != sw))
-                return SMC_ERR_UNSUPPORTED;
-            gmm_kind = q.cfg.move_kind;
-            gmm_sweeps = sw;
-        }
+        if (q.cfg.model == SMC_MODEL_GMM_TEMPERED && (!q.schedule || q.schedule_len < 2))
+            return SMC_ERR_INVALID_ARG;
     }
     const Plan pl = plan(probs, nprob);
     if (table_bytes < pl.total)
@@ -207,10 +295,18 @@ smc_status smc_batch_create(const smc_batch_problem *probs, int32_t nprob, void 
     smc_status s = device_ok(err);
     if (s != SMC_OK)
         return s;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return SMC_ERR_DEVICE;
+    const int per_cu = batch_step_blocks_per_cu();
+    if (per_cu < 1)
+        return SMC_ERR_DEVICE;
     smc_batch *b = new (std::nothrow) smc_batch();
     if (!b)
         return SMC_ERR_DEVICE;
     b->probs.assign(probs, probs + nprob);
+    b->qp = queue_problems(probs, nprob);
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->table = static_cast<char *>(table);
     b->dprobs = reinterpret_cast<Prob *>(b->table + pl.probs);
@@ -218,15 +314,19 @@ smc_status smc_batch_create(const smc_batch_problem *probs, int32_t nprob, void 
     b->map_gmm = reinterpret_cast<int2 *>(b->table + pl.map_gmm);
     b->map_all = reinterpret_cast<int2 *>(b->table + pl.map_all);
     b->step = reinterpret_cast<int32_t *>(b->table + pl.step);
+    b->queue = reinterpret_cast<QItem *>(b->table + pl.queue);
+    b->queue_cap = pl.queue_cap;
+    b->deps = reinterpret_cast<uint32_t *>(b->table + pl.deps);
+    b->sync = reinterpret_cast<uint32_t *>(b->table + pl.sync);
     b->pf_tiles = pl.pf_tiles;
     b->gmm_tiles = pl.gmm_tiles;
     b->all_tiles = pl.pf_tiles + pl.gmm_tiles;
-    b->mala = gmm_kind == SMC_MOVE_MALA;
-    b->sweeps = gmm_sweeps > 0 ? gmm_sweeps : 1;
+    b->cus = prop.multiProcessorCount;
+    b->max_wgs_per_cu = per_cu;
     // descriptors and maps, staged on the host
     std::vector<int2> mpf, mgmm, mall;
-    std::map<int, std::vector<int2>> m64;
-    std::map<int, KGroup> grp;
+    std::map<std::pair<int, bool>, std::vector<int2>> m64;
+    std::map<std::pair<int, bool>, KGroup> grp;
     b->max_steps = 1 << 30;
     for (int32_t i = 0; i < nprob; ++i) {
         const smc_batch_problem &q = probs[i];
@@ -245,12 +345,14 @@ smc_status smc_batch_create(const smc_batch_problem *probs, int32_t nprob, void 
             b->max_steps = std::min<int>(b->max_steps, q.cfg.n_obs - 1);
         } else {
             b->max_steps = std::min<int>(b->max_steps, q.schedule_len - 1);
+            const std::pair<int, bool> key{q.cfg.K, q.cfg.move_kind == SMC_MOVE_MALA};
             const int64_t t64 = ceil_div(q.cfg.n, WAVE);
-            auto &v = m64[q.cfg.K];
+            auto &v = m64[key];
             for (int64_t t = 0; t < t64; ++t)
                 v.push_back(make_int2(i, (int)t));
-            KGroup &g = grp[q.cfg.K];
-            g.K = q.cfg.K;
+            KGroup &g = grp[key];
+            g.K = key.first;
+            g.mala = key.second;
             g.sum_n += q.cfg.n;
             g.max_nd = std::max<int64_t>(g.max_nd, q.cfg.n_data);
         }
@@ -263,15 +365,17 @@ smc_status smc_batch_create(const smc_batch_problem *probs, int32_t nprob, void 
         e = hipMemcpy(b->map_gmm, mgmm.data(), sizeof(int2) * mgmm.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->map_all, mall.data(), sizeof(int2) * mall.size(), hipMemcpyHostToDevice);
-    for (size_t k = 0; k < pl.ks.size() && e == hipSuccess; ++k) {
-        KGroup g = grp[pl.ks[k]];
+    for (size_t k = 0; k < pl.keys.size() && e == hipSuccess; ++k) {
+        KGroup g = grp[pl.keys[k]];
         g.map64 = reinterpret_cast<int2 *>(b->table + pl.map64[k]);
         g.tiles64 = pl.tiles64[k];
         g.W = gmm_waves(g.sum_n, g.max_nd);
-        const auto &v = m64[pl.ks[k]];
+        const auto &v = m64[pl.keys[k]];
         e = hipMemcpy(g.map64, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice);
         b->groups.push_back(g);
     }
+    if (e == hipSuccess)
+        e = set_schedule(b, ORDER_COST_FIRST, 1, per_cu);
     if (e != hipSuccess) {
         delete b;
         return SMC_ERR_DEVICE;
@@ -317,13 +421,16 @@ smc_status smc_batch_init(smc_batch *b)
         e = launch_pf_init_batch(b->dprobs, b->map_pf, b->pf_tiles, s);
     for (const KGroup &g : b->groups)
         if (e == hipSuccess)
-            e = launch_gmm_init_batch(b->dprobs, g.map64, g.tiles64, g.K, g.W, b->mala, s);
+            e = launch_gmm_init_batch(b->dprobs, g.map64, g.tiles64, g.K, g.W, g.mala, s);
     if (e == hipSuccess)
         e = launch_const_partials_batch(b->dprobs, b->map_gmm, b->gmm_tiles, s);
     if (e == hipSuccess)
         e = launch_finalize_batch(b->dprobs, np, b->step, s);
     if (e == hipSuccess)
         e = launch_resample_batch(b->dprobs, b->map_all, b->all_tiles, b->step, s);
+    // the step kernel's tickets and completion counters start from zero
+    if (e == hipSuccess)
+        e = launch_batch_sync_reset(b->sync, b->deps, np, s);
     if (e == hipSuccess) {
         b->initialised = true;
         b->host_step = 0;
@@ -416,82 +523,119 @@ const char *smc_batch_last_error(const smc_batch *b)
     return b ? b->last_error.c_str() : "null batch";
 }
 
+smc_status smc_batch_schedule(const smc_batch *b, int32_t *out)
+{
+    if (!b || !out)
+        return SMC_ERR_INVALID_ARG;
+    out[0] = b->order;
+    out[1] = b->per_item;
+    out[2] = b->wgs_per_cu;
+    out[3] = (int32_t)b->nwg;
+    out[4] = (int32_t)b->nitems;
+    return SMC_OK;
+}
+
+smc_status smc_batch_set_schedule(smc_batch *b, int32_t order, int32_t per_item,
+                                  int32_t wgs_per_cu)
+{
+    if (!b || (order != ORDER_COST_FIRST && order != ORDER_PHASES) || per_item < 1 ||
+        per_item > 2 || wgs_per_cu < 1)
+        return SMC_ERR_INVALID_ARG;
+    return bhip(b, set_schedule(b, order, per_item, wgs_per_cu), "smc_batch_set_schedule");
+}
+
+// Autotuner of the persistent step: times whole steps (from a fresh
+// initialisation) for every candidate schedule -- queue order, 64-particle
+// tiles per Metropolis item, step workgroups per compute unit -- and keeps
+// the fastest; results are cached per device and batch shape bucket.
 smc_status smc_batch_autotune(smc_batch *b, int32_t repeats, const char *cache_path)
 {
     if (!b || repeats < 1)
         return SMC_ERR_INVALID_ARG;
-    std::map<std::string, int> cache;
+    const std::string key = cache_key(b);
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "r")) {
-            char line[512];
+            char line[4096];
+            int o = -1, q = -1, w = -1;
             while (fgets(line, sizeof(line), f)) {
-                char *eq = strrchr(line, '=');
-                char *sp = strstr(line, " W=");
-                if (!eq || !sp)
+                char *tail = strstr(line, " | order=");
+                if (!tail)
                     continue;
-                *sp = 0;
-                cache[line] = atoi(eq + 1);
+                *tail = 0;
+                int oo, qq, ww;
+                if (key == line && sscanf(tail + 3, "order=%d per_item=%d wgs_per_cu=%d", &oo,
+                                          &qq, &ww) == 3) {
+                    o = oo;
+                    q = qq;
+                    w = ww;
+                }
             }
             fclose(f);
+            if ((o == ORDER_COST_FIRST || o == ORDER_PHASES) && (q == 1 || q == 2) && w >= 1) {
+                const hipError_t e = set_schedule(b, o, q, w);
+                b->initialised = false;
+                return bhip(b, e, "smc_batch_autotune (cached schedule)");
+            }
         }
     }
+    const int steps = std::min(repeats + 1, b->max_steps);
+    if (steps < 2)
+        return bfail(b, SMC_ERR_BAD_STATE, "smc_batch_autotune needs two steps of schedule");
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return bfail(b, SMC_ERR_DEVICE, "hipEventCreate");
-    std::vector<std::string> fresh;
+    float best = 1e30f;
+    int bo = b->order, bq = b->per_item, bw = b->wgs_per_cu;
     hipError_t err = hipSuccess;
-    for (KGroup &g : b->groups) {
-        const std::string key = cache_key(g);
-        auto it = cache.find(key);
-        if (it != cache.end() && (it->second == 1 || it->second == 2 || it->second == 4 ||
-                                  it->second == 8)) {
-            g.W = it->second;
-            continue;
-        }
-        float best = 1e30f;
-        int bestW = g.W;
-        for (int W = 1; W <= 8 && err == hipSuccess; W *= 2) {
-            std::vector<float> ms;
-            for (int r = 0; r <= repeats && err == hipSuccess; ++r) {
-                err = hipEventRecord(e0, b->stream);
-                if (err == hipSuccess)
-                    err = launch_gmm_init_batch(b->dprobs, g.map64, g.tiles64, g.K, W, b->mala,
-                                                b->stream);
-                if (err == hipSuccess)
-                    err = hipEventRecord(e1, b->stream);
-                if (err == hipSuccess)
-                    err = hipEventSynchronize(e1);
-                float t = 0.f;
-                if (err == hipSuccess)
-                    err = hipEventElapsedTime(&t, e0, e1);
-                if (r > 0)  // the first launch warms up
-                    ms.push_back(t);
+    for (int o : {ORDER_COST_FIRST, ORDER_PHASES})
+        for (int q = 1; q <= 2; ++q)
+            for (int w = 1; w <= b->max_wgs_per_cu && err == hipSuccess; ++w) {
+                err = set_schedule(b, o, q, w);
+                if (err != hipSuccess)
+                    break;
+                smc_status st = smc_batch_init(b);
+                if (st != SMC_OK) {
+                    err = hipErrorUnknown;
+                    break;
+                }
+                // the first step warms up; the rest are timed one by one
+                std::vector<float> ms;
+                for (int k = 0; k < steps && err == hipSuccess; ++k) {
+                    err = hipEventRecord(e0, b->stream);
+                    if (err == hipSuccess)
+                        err = enqueue_step(b);
+                    if (err == hipSuccess)
+                        err = hipEventRecord(e1, b->stream);
+                    if (err == hipSuccess)
+                        err = hipEventSynchronize(e1);
+                    float t = 0.f;
+                    if (err == hipSuccess)
+                        err = hipEventElapsedTime(&t, e0, e1);
+                    if (k > 0)
+                        ms.push_back(t);
+                }
+                if (err != hipSuccess)
+                    break;
+                std::sort(ms.begin(), ms.end());
+                const float med = ms[ms.size() / 2];
+                if (med < best) {
+                    best = med;
+                    bo = o;
+                    bq = q;
+                    bw = w;
+                }
             }
-            if (err != hipSuccess)
-                break;
-            std::sort(ms.begin(), ms.end());
-            const float med = ms[ms.size() / 2];
-            if (med < best) {
-                best = med;
-                bestW = W;
-            }
-        }
-        g.W = bestW;
-        fresh.push_back(key + " W=" + std::to_string(bestW));
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->initialised = false;
-    if (b->exec) {  // the captured graph used the old tile shapes
-        (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
-    }
+    if (err == hipSuccess)
+        err = set_schedule(b, bo, bq, bw);
     if (err != hipSuccess)
         return bhip(b, err, "smc_batch_autotune");
-    if (cache_path && !fresh.empty()) {
+    if (cache_path) {
         if (FILE *f = fopen(cache_path, "a")) {
-            for (const std::string &l : fresh)
-                fprintf(f, "%s\n", l.c_str());
+            fprintf(f, "%s | order=%d per_item=%d wgs_per_cu=%d step_ms=%.4f\n", key.c_str(), bo,
+                    bq, bw, best);
             fclose(f);
         }
     }

@@ -50,11 +50,14 @@ __host__ __device__ inline Key make_key(uint64_t seed)
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         Key key)
 {
-    uint32_t k0 = key.k0, k1 = key.k1;
-    // The key is wave-uniform: advancing it round by round costs two scalar
-    // adds per round.  The empty asm keeps the compiler from precomputing the
-    // twenty round keys once per kernel and holding them live across every
-    // call (which exhausts the scalar registers of the larger kernels).
+    // The key is wave-uniform (read from the first lane, which also holds
+    // where the compiler cannot prove it, e.g. in a function that is not
+    // inlined): advancing it round by round costs two scalar adds per round.
+    // The empty asm keeps the compiler from precomputing the twenty round
+    // keys once per kernel and holding them live across every call (which
+    // exhausts the scalar registers of the larger kernels).
+    uint32_t k0 = __builtin_amdgcn_readfirstlane(key.k0);
+    uint32_t k1 = __builtin_amdgcn_readfirstlane(key.k1);
     asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {

@@ -6,6 +6,7 @@
 #include <math.h>
 
 #include "smc_gmm_impl.hpp"
+#include "smc_tiles.hpp"
 
 namespace smc {
 
@@ -48,55 +49,10 @@ __global__ void const_partials_batch_kernel(const Prob *__restrict__ probs,
     }
 }
 
-// ---------------------------------------------------------------------------
-// Reweighting of Algorithm "gmm": lw <- (reset ? 0 : lw) + dalpha * l, with
-// dalpha == 0 adding exactly 0; per-tile partials for the normalisation.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void gmm_reweight_tile(const Prob &P, const double *__restrict__ llrow,
-                                                  int64_t tile, int reset_check, double dalpha)
-{
-    __shared__ double red[NWAVES];
-    double *__restrict__ lw = P.lw;
-    const int64_t n = P.n;
-    TilePartial *__restrict__ part = P.partials;
-    const bool reset = reset_check && P.scalars[SMC_S_RESAMPLED] != 0.0;
-    const int64_t base = tile * TILE;
-    double lwv[ITEMS];
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const int64_t i = base + k * TPB + threadIdx.x;
-        lwv[k] = -INFINITY;
-        if (i >= n)
-            continue;
-        const double inc = dalpha == 0.0 ? 0.0 : dalpha * llrow[i];
-        const double l = (reset ? 0.0 : lw[i]) + inc;
-        lw[i] = l;
-        lwv[k] = l;
-    }
-    tile_partial(lwv, part + tile, red);
-}
-
 __global__ __launch_bounds__(TPB) void gmm_reweight_kernel(Prob P, const double *__restrict__ llrow,
                                                            int reset_check, double dalpha)
 {
     gmm_reweight_tile(P, llrow, blockIdx.x, reset_check, dalpha);
-}
-
-// Batched: dalpha from the schedule (0 when alpha_t == 0), the cached
-// log-likelihood of the previous step's state.
-__global__ __launch_bounds__(TPB) void gmm_reweight_batch_kernel(const Prob *__restrict__ probs,
-                                                                 const int2 *__restrict__ map,
-                                                                 const int32_t *__restrict__ step)
-{
-    const int2 pm = map[blockIdx.x];
-    const Prob &P = probs[pm.x];
-    const int32_t t = *step;
-    const double a = fmin(fmax(P.sched[4 * (int64_t)t], 0.0), 1.0);
-    const double ap = fmin(fmax(P.sched[4 * (int64_t)(t - 1)], 0.0), 1.0);
-    const double dalpha = a == 0.0 ? 0.0 : a - ap;
-    const int D = 3 * P.K - 1;
-    const double *llrow = (const double *)P.state[(t - 1) & 1] + (int64_t)D * P.n;
-    gmm_reweight_tile(P, llrow, pm.y, 1, dalpha);
 }
 
 // ---------------------------------------------------------------------------
@@ -189,7 +145,7 @@ hipError_t launch_gmm_loglik_grad(const double *mu, const double *eta, const dou
 }
 
 // ---------------------------------------------------------------------------
-// Batched launchers (one launch per K group; W waves per 64-particle tile)
+// Batched initialisation (one launch per K group; W waves per 64-particle tile)
 // ---------------------------------------------------------------------------
 hipError_t launch_gmm_init_batch(const Prob *probs, const int2 *map64, int64_t tiles64, int K,
                                  int W, bool mala, hipStream_t s)
@@ -199,27 +155,6 @@ hipError_t launch_gmm_init_batch(const Prob *probs, const int2 *map64, int64_t t
 #define CALL_IB(k) GmmK<k>::init_batch(probs, map64, tiles64, W, mala, s)
     SMC_K_SWITCH(K, CALL_IB)
 #undef CALL_IB
-}
-
-hipError_t launch_gmm_block_batch(const Prob *probs, const int2 *map64, int64_t tiles64, int K,
-                                  const int32_t *step, int W, int block, int sweep, int first,
-                                  bool mala, hipStream_t s)
-{
-    if (tiles64 == 0)
-        return hipSuccess;
-#define CALL_BB(k) GmmK<k>::block_batch(probs, map64, tiles64, step, W, block, sweep, first, mala, s)
-    SMC_K_SWITCH(K, CALL_BB)
-#undef CALL_BB
-}
-
-hipError_t launch_gmm_reweight_batch(const Prob *probs, const int2 *map, int64_t tiles,
-                                     const int32_t *step, hipStream_t s)
-{
-    if (tiles == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(gmm_reweight_batch_kernel, dim3((unsigned)tiles), dim3(TPB), 0, s, probs,
-                       map, step);
-    return hipGetLastError();
 }
 
 hipError_t launch_const_partials_batch(const Prob *probs, const int2 *map, int64_t tiles,

@@ -449,16 +449,22 @@ struct BlockStash {
     static constexpr int ROWS = MALA ? 3 + 3 * K - 1 : 3 + K;
 };
 
+// LDS of one Metropolis block: the wave-combine buffer and the stash.
+constexpr int GMM_RED_DOUBLES = GMM_RED_GROUP * GMM_MAXW * WAVE;
+template <int K, bool MALA>
+constexpr int gmm_stash_doubles() { return BlockStash<K, MALA>::ROWS * WAVE; }
+
+// `red` (GMM_RED_DOUBLES) and `stash` (gmm_stash_doubles<K, MALA>()) are the
+// caller's LDS.
 template <int K, bool MALA>
 __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__restrict__ src,
                                                double *__restrict__ dst, int full, int W,
                                                int64_t tile, uint32_t t, int block, int sweep,
-                                               double alpha, double scale, int32_t step)
+                                               double alpha, double scale, int32_t step,
+                                               double *red, double *stash)
 {
     constexpr int D = 3 * K - 1;
     using S = BlockStash<K, MALA>;
-    __shared__ double red[GMM_RED_GROUP * GMM_MAXW * WAVE];
-    __shared__ double stash[S::ROWS * WAVE];
     const int32_t *__restrict__ anc = P.anc;
     const int64_t n = P.n, nd = P.n_data;
     const double *__restrict__ y = P.data;
@@ -597,6 +603,8 @@ __global__ __launch_bounds__(GMM_MAXW *WAVE) void gmm_step_kernel(
     Prob P, const double *__restrict__ src, double *__restrict__ dst, int full, int W, uint32_t t,
     int sweeps, double alpha, double s0, double s1, double s2, int32_t step)
 {
+    __shared__ double red[GMM_RED_DOUBLES];
+    __shared__ double stash[gmm_stash_doubles<K, MALA>()];
     const int nb = K == 1 ? 2 : 3;
     for (int sw = 0; sw < sweeps; ++sw)
         for (int b = 0; b < nb; ++b) {
@@ -604,28 +612,9 @@ __global__ __launch_bounds__(GMM_MAXW *WAVE) void gmm_step_kernel(
             if (!first)
                 __syncthreads();
             gmm_block_tile<K, MALA>(P, first ? src : dst, dst, first ? full : 0, W, blockIdx.x,
-                                    t, b, sw, alpha, b == 0 ? s0 : (b == 1 ? s1 : s2), step);
+                                    t, b, sw, alpha, b == 0 ? s0 : (b == 1 ? s1 : s2), step, red,
+                                    stash);
         }
-}
-
-// Batched: the step, alpha_t and the block scale come from the device (the
-// problem's schedule [T+1][4]); the first block of a step copies the whole
-// state from state[(t-1) & 1] into state[t & 1] (through the ancestors when
-// the step resampled), the others update state[t & 1] in place.
-template <int K, bool MALA>
-__global__ __launch_bounds__(GMM_MAXW *WAVE) void gmm_block_batch_kernel(
-    const Prob *__restrict__ probs, const int2 *__restrict__ map, const int32_t *__restrict__ step,
-    int W, int block, int sweep, int first)
-{
-    const int2 pm = map[blockIdx.x];
-    const Prob &P = probs[pm.x];
-    const int32_t t = *step;
-    const double *sch = P.sched + 4 * (int64_t)t;
-    const double a = fmin(fmax(sch[0], 0.0), 1.0);
-    const double *src = (const double *)P.state[first ? (t - 1) & 1 : t & 1];
-    double *dst = (double *)P.state[t & 1];
-    gmm_block_tile<K, MALA>(P, src, dst, first, W, pm.y, (uint32_t)t, block, sweep, a,
-                            sch[1 + block], t);
 }
 
 // ---------------------------------------------------------------------------
@@ -686,9 +675,6 @@ struct GmmK {
                              const double *y, int64_t nd, double *ll, double *grad, hipStream_t s);
     static hipError_t init_batch(const Prob *probs, const int2 *map, int64_t tiles, int W,
                                  bool mala, hipStream_t s);
-    static hipError_t block_batch(const Prob *probs, const int2 *map, int64_t tiles,
-                                  const int32_t *step, int W, int block, int sweep, int first,
-                                  bool mala, hipStream_t s);
 };
 
 template <int K>
@@ -761,21 +747,6 @@ hipError_t GmmK<K>::init_batch(const Prob *probs, const int2 *map, int64_t tiles
         hipLaunchKernelGGL((gmm_init_batch_kernel<K, true>), grid, blk, 0, s, probs, map, W);
     else
         hipLaunchKernelGGL((gmm_init_batch_kernel<K, false>), grid, blk, 0, s, probs, map, W);
-    return hipGetLastError();
-}
-
-template <int K>
-hipError_t GmmK<K>::block_batch(const Prob *probs, const int2 *map, int64_t tiles,
-                                       const int32_t *step, int W, int block, int sweep,
-                                       int first, bool mala, hipStream_t s)
-{
-    const dim3 grid((unsigned)tiles), blk((unsigned)(W * WAVE));
-    if (mala)
-        hipLaunchKernelGGL((gmm_block_batch_kernel<K, true>), grid, blk, 0, s, probs, map, step,
-                           W, block, sweep, first);
-    else
-        hipLaunchKernelGGL((gmm_block_batch_kernel<K, false>), grid, blk, 0, s, probs, map, step,
-                           W, block, sweep, first);
     return hipGetLastError();
 }
 

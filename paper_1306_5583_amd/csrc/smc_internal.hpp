@@ -72,6 +72,8 @@ struct GmmPrior {
 struct Prob {
     int32_t kind;       // smc_model
     int32_t move_kind;  // GMM: smc_move_kind
+    int32_t elem_bytes; // CV: bytes per state element (8, or 4 for the FP32 state)
+    int32_t sweeps;     // GMM: Metropolis sweeps per step
     int64_t n;          // particles
     int64_t n_data;     // GMM data points / CV observation rows
     int64_t ntiles;     // 1024-particle tiles
@@ -205,8 +207,6 @@ int gmm_waves(int64_t n, int64_t nd);
 
 // --- batched launchers (a table of Prob and (problem, tile) maps) ---
 hipError_t launch_pf_init_batch(const Prob *probs, const int2 *map, int64_t tiles, hipStream_t s);
-hipError_t launch_pf_move_batch(const Prob *probs, const int2 *map, int64_t tiles,
-                                const int32_t *step, hipStream_t s);
 hipError_t launch_finalize_batch(const Prob *probs, int32_t nprob, const int32_t *step,
                                  hipStream_t s);
 hipError_t launch_resample_batch(const Prob *probs, const int2 *map, int64_t tiles,
@@ -215,13 +215,15 @@ hipError_t launch_reset_scalars_batch(const Prob *probs, int32_t nprob, hipStrea
 hipError_t launch_set_step(int32_t *step, int32_t value, int32_t add, hipStream_t s);
 hipError_t launch_gmm_init_batch(const Prob *probs, const int2 *map64, int64_t tiles64, int K,
                                  int W, bool mala, hipStream_t s);
-hipError_t launch_gmm_block_batch(const Prob *probs, const int2 *map64, int64_t tiles64, int K,
-                                  const int32_t *step, int W, int block, int sweep, int first,
-                                  bool mala, hipStream_t s);
-hipError_t launch_gmm_reweight_batch(const Prob *probs, const int2 *map, int64_t tiles,
-                                     const int32_t *step, hipStream_t s);
 hipError_t launch_const_partials_batch(const Prob *probs, const int2 *map, int64_t tiles,
                                        hipStream_t s);
+
+// --- persistent batched step (smc_persist.hip) ---
+struct QItem;
+int batch_step_blocks_per_cu();
+hipError_t launch_batch_step(const Prob *probs, const QItem *queue, uint32_t nitems,
+                             uint32_t nwg, uint32_t *sync, uint32_t *deps, hipStream_t s);
+hipError_t launch_batch_sync_reset(uint32_t *sync, uint32_t *deps, int64_t nprob, hipStream_t s);
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

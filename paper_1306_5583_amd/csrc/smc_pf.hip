@@ -12,7 +12,7 @@
 // problems (blockIdx -> (problem, tile) through a map).
 #include <math.h>
 
-#include "smc_internal.hpp"
+#include "smc_tiles.hpp"
 
 namespace smc {
 
@@ -76,99 +76,6 @@ hipError_t launch_pf_init(Ctx &c)
     else
         hipLaunchKernelGGL(pf_init_kernel<double>, grid, dim3(TPB), 0, c.stream, P);
     return hipGetLastError();
-}
-
-// One move of Algorithm "pf" for the particles of one tile, reading through
-// the pending ancestors, writing the ping-pong partner; with FUSE the
-// incremental log-weight of observation y is added (after a resample the
-// previous weights count as zero) and the tile partial is produced.  With
-// MON the tile also sums w_i and w_i x_i of the incoming population (the
-// monitor of the previous step: w_i = 1 after a resample, else
-// exp(lw_i - M)), column-major into mon[5][ntiles].
-template <typename T, bool FUSE, bool MON>
-__device__ __forceinline__ void pf_move_tile(const Prob &P, const T *__restrict__ xin,
-                                             T *__restrict__ xout, int64_t tile, uint32_t t,
-                                             const double *__restrict__ y, bool gather_check,
-                                             bool reset_check)
-{
-    __shared__ double red[NWAVES];
-    const int64_t n = P.n;
-    double *__restrict__ lw = P.lw;
-    const int32_t *__restrict__ anc = P.anc;
-    const bool resampled =
-        (gather_check || reset_check) ? P.scalars[SMC_S_RESAMPLED] != 0.0 : false;
-    const bool gather = gather_check && resampled;
-    const bool reset = reset_check && resampled;
-    const int64_t base = tile * TILE;
-    const Key key = P.key;
-    const uint32_t p = P.problem_id;
-    const Motion mv = P.mv;
-    const ObsModel obs = P.obs;
-    double yx = 0.0, yy = 0.0;
-    if (FUSE) {
-        yx = y[0];
-        yy = y[1];
-    }
-    const double M = MON ? P.scalars[SMC_S_M] : 0.0;
-    double ms[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    double lwv[ITEMS];
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const int64_t i = base + k * TPB + threadIdx.x;
-        lwv[k] = -INFINITY;
-        if (i >= n)
-            continue;
-        const int64_t src = gather ? (int64_t)anc[i] : i;
-        const T px = xin[src], py = xin[n + src], vx = xin[2 * n + src], vy = xin[3 * n + src];
-        const double lw_in = (FUSE && !reset) || (MON && !reset) ? lw[i] : 0.0;
-        if (MON) {
-            const double w = reset ? 1.0 : exp_nonpos_d(lw_in - M);
-            if (w != 0.0) {
-                ms[0] += w;
-                ms[1] += w * (double)px;
-                ms[2] += w * (double)py;
-                ms[3] += w * (double)vx;
-                ms[4] += w * (double)vy;
-            }
-        }
-        T npx, npy, nvx, nvy;
-        if constexpr (sizeof(T) == 8) {
-            const double2 a = normal2(draw(key, (uint32_t)i, t, TAG_PF_MOVE, 0, p));
-            const double2 b = normal2(draw(key, (uint32_t)i, t, TAG_PF_MOVE, 1, p));
-            npx = (px + mv.dt * vx) + mv.sd_pos * a.x;
-            npy = (py + mv.dt * vy) + mv.sd_pos * a.y;
-            nvx = vx + mv.sd_vel * b.x;
-            nvy = vy + mv.sd_vel * b.y;
-        } else {
-            const float4 z = normal4f(draw(key, (uint32_t)i, t, TAG_PF_MOVE, 0, p));
-            const float dt = (float)mv.dt, sp = (float)mv.sd_pos, sv = (float)mv.sd_vel;
-            npx = (px + dt * vx) + sp * z.x;
-            npy = (py + dt * vy) + sp * z.y;
-            nvx = vx + sv * z.z;
-            nvy = vy + sv * z.w;
-        }
-        xout[i] = npx;
-        xout[n + i] = npy;
-        xout[2 * n + i] = nvx;
-        xout[3 * n + i] = nvy;
-        if (FUSE) {
-            const double inc = obs((double)npx, yx, (double)npy, yy);
-            const double l = lw_in + inc;
-            lw[i] = l;
-            lwv[k] = l;
-        }
-    }
-    if (FUSE)
-        tile_partial(lwv, P.partials + tile, red);
-    if (MON) {
-        __shared__ double red5[5 * NWAVES];
-        block_sum_n<NWAVES, 5>(ms, red5);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int r = 0; r < 5; ++r)
-                P.mon[(int64_t)r * P.ntiles + tile] = ms[r];
-        }
-    }
 }
 
 template <typename T, bool FUSE, bool MON>
@@ -262,30 +169,18 @@ hipError_t launch_pf_reweight(Ctx &c, int32_t obs_index, bool reset_check)
 }
 
 // ---------------------------------------------------------------------------
-// Batched forms: blockIdx -> (problem, tile) through `map`; the step t is
-// read from the device (so one captured graph serves every step); the state
-// of step t lives in state[t & 1].
+// Batched initialisation: blockIdx -> (problem, tile) through `map` (the
+// steps of the batched form run in the persistent step kernel).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(TPB) void pf_init_batch_kernel(const Prob *__restrict__ probs,
                                                             const int2 *__restrict__ map)
 {
     const int2 pm = map[blockIdx.x];
     const Prob &P = probs[pm.x];
-    pf_init_tile<double>(P, (double *)P.state[0], pm.y);
-}
-
-__global__ __launch_bounds__(TPB) void pf_move_batch_kernel(const Prob *__restrict__ probs,
-                                                            const int2 *__restrict__ map,
-                                                            const int32_t *__restrict__ step)
-{
-    const int2 pm = map[blockIdx.x];
-    const Prob &P = probs[pm.x];
-    const int32_t t = *step;
-    const double *xin = (const double *)P.state[(t - 1) & 1];
-    double *xout = (double *)P.state[t & 1];
-    const int32_t obs = t < P.n_data ? t : (int32_t)P.n_data - 1;
-    pf_move_tile<double, true, true>(P, xin, xout, pm.y, (uint32_t)t, P.data + 2 * (int64_t)obs,
-                                     true, true);
+    if (P.elem_bytes == 4)
+        pf_init_tile<float>(P, (float *)P.state[0], pm.y);
+    else
+        pf_init_tile<double>(P, (double *)P.state[0], pm.y);
 }
 
 hipError_t launch_pf_init_batch(const Prob *probs, const int2 *map, int64_t tiles, hipStream_t s)
@@ -293,16 +188,6 @@ hipError_t launch_pf_init_batch(const Prob *probs, const int2 *map, int64_t tile
     if (tiles == 0)
         return hipSuccess;
     hipLaunchKernelGGL(pf_init_batch_kernel, dim3((unsigned)tiles), dim3(TPB), 0, s, probs, map);
-    return hipGetLastError();
-}
-
-hipError_t launch_pf_move_batch(const Prob *probs, const int2 *map, int64_t tiles,
-                                const int32_t *step, hipStream_t s)
-{
-    if (tiles == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(pf_move_batch_kernel, dim3((unsigned)tiles), dim3(TPB), 0, s, probs, map,
-                       step);
     return hipGetLastError();
 }
 

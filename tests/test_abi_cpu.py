@@ -159,16 +159,26 @@ def test_batch_host_validation(L):
             L.smc_batch_create(probs, table, nb, None)
         return e.value.status
 
-    # resampling other than systematic, FP32 filter state: not batched
+    # multinomial resampling and mixtures beyond K = 8 are not batched
+    # (table_size already refuses them); FP32 filter state, stratified
+    # resampling and mixed move kinds are (no device here: they end in
+    # SMC_ERR_DEVICE)
+    with pytest.raises(L.SmcError) as e:
+        L.smc_batch_table_size([_fake_problem(L, L.make_config(L.SMC_MODEL_CV_TRACK, 10,
+                                                               n_obs=3, scheme="multinomial"))])
+    assert e.value.status == L.SMC_ERR_UNSUPPORTED
     assert create([_fake_problem(L, L.make_config(L.SMC_MODEL_CV_TRACK, 10, n_obs=3,
-                                                  scheme="multinomial"))]) == \
+                                                  scheme="multinomial"))], one) == \
         L.SMC_ERR_UNSUPPORTED
+    k9 = L.make_config(L.SMC_MODEL_GMM_TEMPERED, 3000, K=9, n_data=50)
+    assert create([_fake_problem(L, k9, sched)], two) == L.SMC_ERR_UNSUPPORTED
     assert create([_fake_problem(L, L.make_config(L.SMC_MODEL_CV_TRACK, 10, n_obs=3,
                                                   precision=L.SMC_F32_STATE))]) == \
-        L.SMC_ERR_UNSUPPORTED
-    # samplers of one batch share the move kind
+        L.SMC_ERR_DEVICE
+    assert create([_fake_problem(L, L.make_config(L.SMC_MODEL_CV_TRACK, 10, n_obs=3,
+                                                  scheme="stratified"))]) == L.SMC_ERR_DEVICE
     assert create([_fake_problem(L, rw, sched), _fake_problem(L, mala, sched)]) == \
-        L.SMC_ERR_UNSUPPORTED
+        L.SMC_ERR_DEVICE
     # a sampler needs its schedule; the table must be large enough
     assert create([_fake_problem(L, rw)]) == L.SMC_ERR_INVALID_ARG
     assert create([_fake_problem(L, pf)], one - 256) == L.SMC_ERR_INVALID_ARG

@@ -171,6 +171,9 @@ def test_step_limits_and_order(lib):
 
 
 def test_autotune_and_cache(lib, tmp_path):
+    # the tuner times whole steps for every schedule candidate; a schedule
+    # only changes which workgroup takes which item, never the arithmetic,
+    # so the tuned run is bit-identical to the default one
     pkg, L = lib
     steps = 5
     work = _small_workload(steps)
@@ -179,21 +182,104 @@ def test_autotune_and_cache(lib, tmp_path):
     ref = pkg.BatchRunner(_specs(pkg, work))
     ref.run(steps, graph=True)
     br.autotune(repeats=3, cache_path=cache)
-    Ks = sorted({kw["K"] for k, kw in work if k == "gmm"})
-    chosen = {K: br.waves(K) for K in Ks}
-    assert all(w in (1, 2, 4, 8) for w in chosen.values())
+    sch = br.schedule()
+    _say("tuned schedule", sch)
+    assert sch["order"] in (0, 1) and sch["per_item"] in (1, 2) and sch["wgs_per_cu"] >= 1
+    assert sch["workgroups"] >= 256 * sch["wgs_per_cu"] // 2
     lines = open(cache).read().strip().splitlines()
-    assert len(lines) == len(Ks)
+    assert len(lines) == 1 and "order=%d per_item=%d wgs_per_cu=%d" % (
+        sch["order"], sch["per_item"], sch["wgs_per_cu"]) in lines[0]
     br.run(steps, graph=True)
     br.check()
-    for i, (kind, kw) in enumerate(work):
-        scale = max(1.0, np.abs(ref.history_host(i)[:, L.SMC_H_DLOGZ]).sum())
-        assert abs(br.log_z(i) - ref.log_z(i)) <= 1e-10 * scale, i
+    for i in range(len(work)):
+        assert np.array_equal(br.history_host(i), ref.history_host(i)), i
+        assert np.array_equal(br.state(i).cpu().numpy(), ref.state(i).cpu().numpy()), i
     # a second tuner call reads the cache and does not append
     br2 = pkg.BatchRunner(_specs(pkg, work))
     br2.autotune(repeats=3, cache_path=cache)
-    assert {K: br2.waves(K) for K in Ks} == chosen
+    assert br2.schedule() == sch
     assert open(cache).read().strip().splitlines() == lines
+
+
+def test_every_schedule_gives_the_same_bits(lib):
+    # queue orders, tiles per Metropolis item and workgroup counts: the
+    # dependency waits make every schedule compute the same thing
+    pkg, L = lib
+    steps = 4
+    work = _small_workload(steps)
+    ref = None
+    for order, per_item, wgs in [(0, 1, 2), (1, 2, 1), (0, 2, 1), (1, 1, 2)]:
+        br = pkg.BatchRunner(_specs(pkg, work))
+        L.load()
+        br.set_schedule(order, per_item, wgs)
+        br.run(steps, graph=(order == 0))
+        br.check()
+        got = [(br.history_host(i).copy(), br.state(i).cpu().numpy().copy())
+               for i in range(len(work))]
+        _say("schedule", order, per_item, wgs, br.schedule())
+        if ref is None:
+            ref = got
+        else:
+            for i, ((h0, x0), (h1, x1)) in enumerate(zip(ref, got)):
+                assert np.array_equal(h0, h1), (order, per_item, wgs, i)
+                assert np.array_equal(x0, x1), (order, per_item, wgs, i)
+        br.close()
+
+
+def test_batch_variants_match_oracle(lib, orc):
+    """What the single-problem contexts allow, batched: FP32 filter state,
+    stratified resampling for filters and samplers, random-walk and MALA
+    samplers in one batch, two Metropolis sweeps."""
+    pkg, L = lib
+    steps = 8
+    rng = np.random.default_rng(77)
+    base = [synth.BatchProblem("pf", 3001, 11, 21), synth.BatchProblem("pf", 2048, 12, 22),
+            synth.BatchProblem("gmm", 2500, 13, 23, 3, 80), synth.BatchProblem("gmm", 1800, 14, 24, 4, 60),
+            synth.BatchProblem("gmm", 1100, 15, 25, 2, 50)]
+    work = synth.batched_workload(steps, base)
+    specs = [pkg.PfSpec(fp32_state=True, **work[0][1]),
+             pkg.PfSpec(scheme="stratified", **work[1][1]),
+             pkg.GmmSpec(move="rw", scheme="stratified", **work[2][1]),
+             pkg.GmmSpec(move="mala", sweeps=2, **work[3][1]),
+             pkg.GmmSpec(move="rw", **work[4][1])]
+    br = pkg.BatchRunner(specs)
+    br.run(steps, graph=True)
+    br.check()
+    # tracking filters: the FP32 state against the single-problem FP32 filter
+    # bit for bit (two independent FP32 runs drift apart by resampling flips,
+    # so FP32 parity with the oracle is the lock-step test's), the stratified
+    # FP64 filter against the oracle end to end
+    kw = work[0][1]
+    pf = pkg.ParticleFilter(kw["n"], kw["y"], seed=kw["seed"], problem_id=kw["problem_id"],
+                            fp32_state=True)
+    pf.run()
+    hs = pf.history_host()
+    cols = [L.SMC_H_ESS, L.SMC_H_FLAG, L.SMC_H_DLOGZ, L.SMC_H_LOGZ, L.SMC_H_L]
+    assert np.array_equal(br.history_host(0)[:, cols], hs[:, cols])
+    assert np.array_equal(br.state(0).cpu().numpy(), pf.state().cpu().numpy())
+    pf.close()
+    kw = work[1][1]
+    cfg = orc.pf_cfg(kw["n"], kw["seed"], problem=kw["problem_id"], scheme="stratified")
+    logz_o, hist_o, xf_o, _ = orc.pf_run(cfg, kw["y"])
+    h = br.history_host(1)
+    scale = max(1.0, np.abs(hist_o[:, 2]).sum())
+    assert abs(br.log_z(1) - logz_o) <= 1e-12 * scale, (br.log_z(1), logz_o)
+    assert np.array_equal(h[:steps + 1, L.SMC_H_FLAG], hist_o[:, 1])
+    assert_close_l1(h[:steps + 1, L.SMC_H_ESS], hist_o[:, 0], hist_o[:, 0], 1e-11, "ess")
+    # mixture samplers
+    for i, (move, sweeps, scheme) in [(2, ("rw", 1, "stratified")), (3, ("mala", 2, "systematic")),
+                                      (4, ("rw", 1, "systematic"))]:
+        kw = work[i][1]
+        sched = pkg.batch.gmm_schedule(kw["alphas"], None, move)
+        cfg = orc.gmm_cfg(kw["n"], kw["seed"], kw["K"], problem=kw["problem_id"], move=move,
+                          sweeps=sweeps, scheme=scheme)
+        logz_o, hist_o, pop_o, _ = orc.gmm_run(cfg, kw["y"], sched[:, 0], sched[:, 1:])
+        ts = assert_gmm_run_matches(br.history_host(i)[:steps + 1], hist_o, sched[:, 0], L,
+                                    "problem %d" % i, path=False)
+        assert ts == steps + 1, (i, ts)
+        D = 3 * kw["K"] - 1
+        st = br.state(i).cpu().numpy()[:D]
+        assert_close_l1(st, pop_o, np.abs(pop_o) + 1.0, 1e-12, "problem %d population" % i)
 
 
 def test_full_size_batched_workload_sampled(lib, orc):
