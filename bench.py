@@ -43,7 +43,8 @@ CSRC = os.path.join(ROOT, "paper_1306_5583_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 
 # sources whose change invalidates a stored counter measurement
-PF_MOVE_SOURCES = ["smc_pf.hip", "smc_device.hpp", "smc_math.hpp", "smc_internal.hpp"]
+PF_MOVE_SOURCES = ["smc_pf.hip", "smc_tiles.hpp", "smc_device.hpp", "smc_math.hpp",
+                   "smc_internal.hpp"]
 GMM_BLOCK_SOURCES = ["smc_gmm_impl.hpp", "smc_device.hpp", "smc_math.hpp", "smc_internal.hpp"]
 
 
@@ -635,15 +636,22 @@ def bench_models(args):
 # ------------------------------------------------- MALA vs random walk study
 
 def _method_scales(method, alphas):
-    """'mala' / 'mala:h' (MALA step h, default 0.05) or 'rw' / 'rw:b' (random
-    walk with the paper's per-block scales rescaled to base b, default 0.15):
-    the move kind and the per-step block scales."""
+    """'mala' / 'mala:h' (MALA step h, default 0.05; 'malaad:h' the same
+    steps times per-block factors that follow the acceptance rates, see
+    BlockAdapter), 'rw' / 'rw:b' ('rwad:b' acceptance-adapted) (random
+    walk with the paper's alpha-adaptive per-block scales rescaled to base b,
+    default 0.15) or 'rwfixed:s' (random walk with the same standard
+    deviation s in every block and step): the move kind and the per-step
+    block scales."""
     from paper_1306_5583_amd import mala_scales, rw_scales
     kind, _, par = method.partition(":")
-    if kind == "mala":
+    if kind in ("mala", "malaad"):
         h = float(par) if par else 0.05
         return "mala", np.array([mala_scales(min(max(a, 0.0), 1.0), h) for a in alphas])
-    b = float(par) if par else 0.15
+    if kind == "rwfixed":
+        sd = float(par) if par else 0.15
+        return "rw", np.full((len(alphas), 3), sd)
+    b = float(par) if par else 0.15  # 'rw' and 'rwad' (the same, acceptance-adapted)
     return "rw", np.array([rw_scales(min(max(a, 0.0), 1.0), b) for a in alphas])
 
 
@@ -658,12 +666,20 @@ def _study_batch(y, K, n, T, method, seeds, seed0):
     specs = [pkg.GmmSpec(n=n, y=y, K=K, alphas=alphas, scales=scales, move=move,
                          seed=seed0 + s, problem_id=s) for s in range(seeds)]
     br = pkg.BatchRunner(specs)
+    adapt = method.startswith(("malaad", "rwad"))
+    ads = [pkg.BlockAdapter(move) for _ in range(seeds)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     br.init()
     br.capture()
     for k in range(T):
         br.replay()
+        if adapt and k + 1 < T:
+            # each sampler's block scales follow its acceptance rates
+            # (BlockAdapter: towards 0.574 for MALA, 0.234 for the random walk)
+            acc = br.accept_counts(k + 1)
+            for s in range(seeds):
+                br.set_block_scales(s, k + 2, scales[k + 2] * ads[s].update(acc[s], n))
         if (k + 1) % 200 == 0 and k + 1 < T:
             # a progress line per 200 steps (long configurations run for minutes)
             br.stream.synchronize()

@@ -362,7 +362,9 @@ smc_status smc_profile_read(smc_ctx *ctx, float *ms, int32_t capacity, int32_t *
  * independent filters and samplers of different sizes advanced together,
  * each step ONE launch of a persistent kernel whose workgroups take work
  * items -- (problem, phase, tile): move / reweight tiles, normalisations,
- * resampling tiles, Metropolis tiles -- from a queue in ticket order,
+ * resampling tiles, Metropolis tiles, the samplers' path-sampling monitor
+ * (history columns SMC_H_PATH, SMC_H_PS; scalar SMC_S_PS_LOGZ, with the
+ * step-0 point taken by smc_batch_init) -- from a queue in ticket order,
  * waiting on per-problem completion counters for the items each depends
  * on.  The queue lists every item after the items it waits for, so the
  * step progresses whatever the number of co-resident workgroups; waits are
@@ -400,7 +402,8 @@ smc_status smc_batch_table_size(const smc_batch_problem *probs, int32_t nprob, s
  * items; order 1 = phase by phase in problem order.  per_item (1 or 2)
  * 64-particle tiles make one Metropolis item.  items receives *count rows of
  * four int32 {kind (0 move, 1 reweight, 2 normalise, 3 resample, 4
- * Metropolis), problem, tile, tiles in the item}; with capacity 0 only
+ * Metropolis, 5 monitor), problem, tile, tiles in the item (monitor: the
+ * problem's Metropolis items)}; with capacity 0 only
  * *count is written.  SMC_ERR_INVALID_ARG when capacity is non-zero and too
  * small. */
 smc_status smc_batch_plan_queue(const smc_batch_problem *probs, int32_t nprob, int32_t order,

@@ -8,11 +8,12 @@ from ._lib import SmcError
 
 _lib.load()
 
-from .sampler import GmmSampler, ParticleFilter, mala_scales, rw_scales  # noqa: E402
+from .sampler import (BlockAdapter, GmmSampler, ParticleFilter, mala_scales,  # noqa: E402
+                      rw_scales)
 
 from .autograd import GmmLogLik, gmm_loglik  # noqa: E402
 
 from .batch import BatchRunner, GmmSpec, PfSpec  # noqa: E402
 
 __all__ = ["ParticleFilter", "GmmSampler", "GmmLogLik", "gmm_loglik", "rw_scales",
-           "mala_scales", "SmcError", "BatchRunner", "PfSpec", "GmmSpec"]
+           "mala_scales", "BlockAdapter", "SmcError", "BatchRunner", "PfSpec", "GmmSpec"]

@@ -18,7 +18,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from .sampler import ProblemBuffers, mala_scales, rw_scales
+from .sampler import BlockAdapter, ProblemBuffers, mala_scales, rw_scales
 
 
 @dataclasses.dataclass
@@ -73,6 +73,7 @@ class BatchRunner:
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.bufs: List[ProblemBuffers] = []
         self.schedules: List[Optional[torch.Tensor]] = []
+        self._base_scales = {}   # mixture sampler index -> its schedule's block scales
         probs = []
         for sp in self.specs:
             bp = L.smc_batch_problem()
@@ -89,8 +90,9 @@ class BatchRunner:
                 bp.schedule_len = 0
             elif isinstance(sp, GmmSpec):
                 y = torch.as_tensor(np.ascontiguousarray(sp.y, dtype=np.float64))
-                sched = torch.as_tensor(gmm_schedule(sp.alphas, sp.scales, sp.move),
-                                        device=self.device)
+                sched_h = gmm_schedule(sp.alphas, sp.scales, sp.move)
+                self._base_scales[len(self.schedules)] = sched_h[:, 1:4].copy()
+                sched = torch.as_tensor(sched_h, device=self.device)
                 S = int(sched.shape[0]) - 1
                 cfg = L.make_config(L.SMC_MODEL_GMM_TEMPERED, sp.n, seed=sp.seed,
                                     problem_id=sp.problem_id, threshold=sp.threshold, K=sp.K,
@@ -162,14 +164,27 @@ class BatchRunner:
         L.smc_batch_replay(self.handle)
         self.steps_done += 1
 
-    def run(self, steps: int, graph: bool = True, latencies: bool = False):
+    def run(self, steps: int, graph: bool = True, latencies: bool = False, adapt: bool = False):
         """init, then `steps` steps (graph replays when graph=True).  With
         latencies=True returns the per-step times in ms (events around
-        every step on the batch stream)."""
+        every step on the batch stream).  With adapt, every mixture
+        sampler's block scales follow its acceptance rates (BlockAdapter:
+        after each step the host reads the step's acceptance counts and
+        rewrites the next step's schedule row)."""
         self.init()
         if graph:
             self.capture()
         go = self.replay if graph else self.step
+        if adapt:
+            ad = {i: BlockAdapter(self.specs[i].move) for i in self._base_scales}
+            for k in range(steps):
+                go()
+                if k + 1 < steps:
+                    acc = self.accept_counts(k + 1)
+                    for i, a in ad.items():
+                        f = a.update(acc[i], self.specs[i].n)
+                        self.set_block_scales(i, k + 2, self._base_scales[i][k + 2] * f)
+            return []
         times = []
         if latencies:
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
@@ -200,9 +215,36 @@ class BatchRunner:
         b = self.bufs[i]
         return b.state_a if self.steps_done % 2 == 0 else b.state_b
 
+    def accept_counts(self, t: int) -> np.ndarray:
+        """Accepted proposals per Metropolis block at step t, [problems][3]
+        (zeros for tracking filters)."""
+        self.stream.synchronize()
+        return np.stack([b.history[t, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3].cpu().numpy()
+                         for b in self.bufs])
+
+    def schedule_host(self, i: int) -> np.ndarray:
+        """Rows [alpha_t, s_mu, s_eta, s_z] mixture sampler i runs with (after
+        an adaptive run: the scales it used)."""
+        self.stream.synchronize()
+        return self.schedules[i].cpu().numpy()
+
+    def set_block_scales(self, i: int, t: int, scales) -> None:
+        """Overwrites the block scales of problem i at step t (its schedule
+        row), in stream order: steps enqueued later read the new row."""
+        row = torch.as_tensor(np.asarray(scales, dtype=np.float64).reshape(3))
+        with torch.cuda.stream(self.stream):
+            self.schedules[i][t, 1:4].copy_(row)
+        self.stream.synchronize()
+
     def history_host(self, i: int) -> np.ndarray:
         self.stream.synchronize()
         return self.bufs[i].history.cpu().numpy()
+
+    def log_z_path(self, i: int) -> float:
+        """Path-sampling estimate of log Z of mixture sampler i (Section 5.2:
+        the trapezoid over the schedule of U_t = sum_i W_i l(theta_i))."""
+        self.stream.synchronize()
+        return float(self.bufs[i].scalars[L.SMC_S_PS_LOGZ].item())
 
     def log_z(self, i: int) -> float:
         self.stream.synchronize()

@@ -86,7 +86,7 @@ Plan plan(const smc_batch_problem *probs, int32_t np)
         } else {
             pl.gmm_tiles += nt;
             t64[{c.K, c.move_kind == SMC_MOVE_MALA}] += ceil_div(c.n, WAVE);
-            pl.queue_cap += 2 * nt + 1 + ceil_div(c.n, WAVE);
+            pl.queue_cap += 2 * nt + 2 + ceil_div(c.n, WAVE);
         }
     }
     size_t off = 0;
@@ -428,6 +428,9 @@ smc_status smc_batch_init(smc_batch *b)
         e = launch_finalize_batch(b->dprobs, np, b->step, s);
     if (e == hipSuccess)
         e = launch_resample_batch(b->dprobs, b->map_all, b->all_tiles, b->step, s);
+    // the mixture samplers' step-0 path-sampling point (alpha_0, U_0)
+    if (e == hipSuccess && b->gmm_tiles > 0)
+        e = launch_batch_monitor0(b->dprobs, np, s);
     // the step kernel's tickets and completion counters start from zero
     if (e == hipSuccess)
         e = launch_batch_sync_reset(b->sync, b->deps, np, s);

@@ -13,20 +13,29 @@
 namespace smc {
 
 // Kinds of work item (see smc_persist.hip for what each does).
-enum : int32_t { IT_PF_MOVE = 0, IT_GMM_REWEIGHT = 1, IT_FINAL = 2, IT_RESAMPLE = 3, IT_GMM_STEP = 4 };
+enum : int32_t {
+    IT_PF_MOVE = 0,
+    IT_GMM_REWEIGHT = 1,
+    IT_FINAL = 2,
+    IT_RESAMPLE = 3,
+    IT_GMM_STEP = 4,
+    IT_MONITOR = 5  // mixture sampler: path-sampling integrand after all its M items
+};
 
 struct QItem {
     int32_t kind;
     int32_t prob;
     int32_t tile;   // 1024-particle tile (A, R), 64-particle tile (M); 0 for F
-    int32_t count;  // M: consecutive 64-particle tiles of the item; 1 otherwise
+    int32_t count;  // M: consecutive 64-particle tiles of the item; monitor: the
+                    // problem's M items per step; 1 otherwise
 };
 
 // Per-problem completion counters (uint32 each, DEP_STRIDE per problem):
 // DEP_A counts finished A tiles, DEP_F finished normalisations, DEP_R
-// finished resampling tiles of mixture samplers.  At step t the targets are
-// t * tiles (A, R) and t (F).
-enum : int { DEP_A = 0, DEP_F = 1, DEP_R = 2, DEP_STRIDE = 4 };
+// finished resampling tiles of mixture samplers, DEP_M their finished
+// Metropolis items.  At step t the targets are t * tiles (A, R), t (F) and
+// t * M items (the monitor).
+enum : int { DEP_A = 0, DEP_F = 1, DEP_R = 2, DEP_M = 3, DEP_STRIDE = 4 };
 // Launch-wide words: the ticket counter and the abort flag.
 enum : int { SYNC_TICKET = 0, SYNC_ABORT = 1, SYNC_WORDS = 64 };
 
@@ -36,11 +45,12 @@ constexpr int BATCH_MAX_K = 8;
 // Orders of the queue the autotuner chooses between.
 enum : int32_t {
     // mixture samplers' A, F, R items, then their Metropolis tiles with the
-    // most expensive problems first, then the tracking filters' items (which
-    // fill the workgroups freed at the tail of the Metropolis phase)
+    // most expensive problems first and their monitors, then the tracking
+    // filters' items (which fill the workgroups freed at the tail of the
+    // Metropolis phase)
     ORDER_COST_FIRST = 0,
     // phase by phase in problem order: every A item, every F, every R, then
-    // the Metropolis tiles
+    // the Metropolis tiles and the monitors
     ORDER_PHASES = 1
 };
 
@@ -80,6 +90,11 @@ inline std::vector<QItem> build_queue(const std::vector<QProblem> &pr, int32_t o
                 q.push_back(QItem{IT_GMM_STEP, p, (int32_t)b,
                                   (int32_t)std::min<int64_t>(per_item, pr[p].tiles64 - b)});
     };
+    auto phase_mon = [&](const std::vector<int> &ps) {
+        for (int p : ps)
+            q.push_back(QItem{IT_MONITOR, p, 0,
+                              (int32_t)((pr[p].tiles64 + per_item - 1) / per_item)});
+    };
     if (order == ORDER_PHASES) {
         std::vector<int> all(np);
         for (int p = 0; p < np; ++p)
@@ -88,6 +103,7 @@ inline std::vector<QItem> build_queue(const std::vector<QProblem> &pr, int32_t o
         phase_f(all);
         phase_r(all);
         phase_m(gm);
+        phase_mon(gm);
     } else {
         std::vector<int> byc = gm;
         std::stable_sort(byc.begin(), byc.end(),
@@ -96,6 +112,7 @@ inline std::vector<QItem> build_queue(const std::vector<QProblem> &pr, int32_t o
         phase_f(byc);
         phase_r(byc);
         phase_m(byc);
+        phase_mon(byc);
         phase_a(pf);
         phase_f(pf);
         phase_r(pf);

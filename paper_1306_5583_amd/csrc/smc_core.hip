@@ -100,6 +100,7 @@ __global__ void reset_scalars_batch_kernel(const Prob *__restrict__ probs)
         P.scalars[SMC_S_L] = log((double)P.n);
         P.scalars[SMC_S_L2] = log((double)P.n);
         P.scalars[SMC_S_ESS] = (double)P.n;
+        P.scalars[SMC_S_PS_ALPHA] = -1.0;
     }
 }
 

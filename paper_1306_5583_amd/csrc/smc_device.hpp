@@ -160,9 +160,10 @@ __device__ inline double gamma_draw(Key key, uint32_t i, uint32_t t, uint32_t ta
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic reductions.  Butterfly (xor) exchanges leave every lane of a
-// wave with the same value; workgroup results combine the per-wave values in
-// wave order.
+// Deterministic reductions.  Within a wave, DPP row shifts and row
+// broadcasts (below) build the inclusive scan or the reduction in a fixed
+// order, and the result is read back from the last lane; workgroup results
+// combine the per-wave values in wave order.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }

@@ -14,7 +14,9 @@
 //      monitor of the previous step;
 //   R  resampling of one 1024-particle tile (after its F);
 //   M  mixture sampler: every Metropolis block and sweep of one or two
-//      64-particle tiles (after all its R tiles).
+//      64-particle tiles (after all its R tiles);
+//   U  mixture sampler: the path-sampling integrand and trapezoid (after all
+//      its M items).
 // Per-problem completion counters only ever grow (a step's targets are
 // multiples of the step index), so nothing is reset between steps; the step
 // index itself comes from the ticket: a step consumes exactly
@@ -111,6 +113,49 @@ __device__ __forceinline__ void gmm_item_dispatch(const Prob &P, int64_t tile0, 
 #undef SMC_GMM_ITEM
 }
 
+// Path-sampling integrand of a mixture sampler at step t (Eq. path_import:
+// U_t = sum_i W_i l_i over the population after the Metropolis moves) and
+// one trapezoid of Eq. path_est, as the single-problem sampler's monitor
+// takes them: per 64-particle tile the sums of w_i and w_i l_i (w_i = 1
+// after a resample, else exp(lw_i - M)) in the tile's wave, written
+// column-major to the problem's monitor partials, then combined over the
+// tiles in a fixed order by the workgroup.
+__device__ __forceinline__ void gmm_path_monitor(const Prob &P, int32_t t)
+{
+    const int64_t n = P.n, t64 = ceil_div(n, WAVE);
+    const int D = 3 * P.K - 1;
+    const double *__restrict__ ll = (const double *)P.state[t & 1] + (int64_t)D * n;
+    const bool reset = P.scalars[SMC_S_RESAMPLED] != 0.0;
+    const double M = P.scalars[SMC_S_M];
+    for (int64_t b = wave_id(); b < t64; b += NWAVES) {
+        const int64_t i = b * WAVE + lane_id();
+        double w = 0.0, wl = 0.0;
+        if (i < n) {
+            w = reset ? 1.0 : exp_nonpos_d(P.lw[i] - M);
+            if (w != 0.0)
+                wl = w * ll[i];
+        }
+        w = wave_sum(w);
+        wl = wave_sum(wl);
+        if (lane_id() == 0) {
+            P.mon[b] = w;
+            P.mon[t64 + b] = wl;
+        }
+    }
+    __syncthreads();
+    __shared__ double red[MON_STRIDE * NWAVES];
+    __shared__ double col[MON_STRIDE];
+    MonDest md;
+    md.step = t;
+    md.rows = 1;
+    md.hist_col = SMC_H_PATH;
+    md.hist_ncols = 1;
+    md.out = nullptr;
+    md.scalars = P.scalars;
+    md.alpha = fmin(fmax(P.sched[4 * (int64_t)t], 0.0), 1.0);
+    mon_combine<TPB>(P.mon, t64, md, P.hist, P.hist_len, red, col);
+}
+
 __global__ __launch_bounds__(TPB, 2) void batch_step_kernel(const Prob *__restrict__ probs,
                                                          const QItem *__restrict__ queue,
                                                          uint32_t nitems, uint32_t per_step,
@@ -157,6 +202,9 @@ __global__ __launch_bounds__(TPB, 2) void batch_step_kernel(const Prob *__restri
             } else if (it.kind == IT_GMM_STEP) {
                 dkind = DEP_R;
                 target = (uint32_t)t * ntl;
+            } else if (it.kind == IT_MONITOR) {
+                dkind = DEP_M;
+                target = (uint32_t)t * (uint32_t)it.count;
             }
             if (go && dkind >= 0 && !(ok_prob == it.prob && ok_kind == dkind)) {
                 go = wait_at_least(dc + dkind, target, &sync[SYNC_ABORT],
@@ -224,6 +272,10 @@ __global__ __launch_bounds__(TPB, 2) void batch_step_kernel(const Prob *__restri
             break;
         case IT_GMM_STEP:
             gmm_item_dispatch(P, it.tile, it.count, t, gred, gstash);
+            release = DEP_M;
+            break;
+        case IT_MONITOR:
+            gmm_path_monitor(P, t);
             break;
         default:
             break;
@@ -232,6 +284,15 @@ __global__ __launch_bounds__(TPB, 2) void batch_step_kernel(const Prob *__restri
         if (release >= 0 && tid == 0)
             __hip_atomic_fetch_add(dc + release, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// The mixture samplers' step-0 monitor (the prior draws, alpha_0): one
+// workgroup per problem, filters skipped.
+__global__ __launch_bounds__(TPB) void batch_monitor0_kernel(const Prob *__restrict__ probs)
+{
+    const Prob &P = probs[blockIdx.x];
+    if (P.kind == SMC_MODEL_GMM_TEMPERED)
+        gmm_path_monitor(P, 0);
 }
 
 __global__ void batch_sync_reset_kernel(uint32_t *sync, uint32_t *deps, int64_t ndeps)
@@ -258,6 +319,12 @@ hipError_t launch_batch_step(const Prob *probs, const QItem *queue, uint32_t nit
 {
     hipLaunchKernelGGL(batch_step_kernel, dim3(nwg), dim3(TPB), 0, s, probs, queue, nitems,
                        nitems + nwg, sync, deps);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_monitor0(const Prob *probs, int32_t nprob, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_monitor0_kernel, dim3((unsigned)nprob), dim3(TPB), 0, s, probs);
     return hipGetLastError();
 }
 

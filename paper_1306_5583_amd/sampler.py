@@ -177,6 +177,31 @@ def mala_scales(alpha: float, step: float = 0.05):
     return tuple(step * s / 0.15 for s in rw_scales(alpha))
 
 
+# Acceptance rates the adaptive step sizes steer towards: the asymptotically
+# optimal rates of Langevin (Roberts & Rosenthal 1998) and random-walk
+# (Roberts, Gelman & Gilks 1997) proposals.
+TARGET_ACCEPT = {"mala": 0.574, "rw": 0.234}
+
+
+class BlockAdapter:
+    """Per-block step sizes adapted to the population's acceptance rates:
+    the scales of step t + 1 are the base scales of that step times factors
+    f_b <- clip(f_b exp(a_b - target), 0.05, 20), a_b the fraction of
+    proposals of block b accepted at step t (all particles).  The factors
+    depend only on past steps of the run, so the target distributions and
+    the estimators are unchanged (an adaptive SMC sampler); the scales used
+    are recorded, and a run can be replayed with them."""
+
+    def __init__(self, move: str, blocks: int = 3):
+        self.target = TARGET_ACCEPT[move]
+        self.f = np.ones(blocks)
+
+    def update(self, accepted, n: int) -> np.ndarray:
+        rate = np.asarray(accepted, dtype=np.float64) / float(n)
+        self.f = np.clip(self.f * np.exp(rate - self.target), 0.05, 20.0)
+        return self.f
+
+
 class GmmSampler(_Base):
     """Tempered SMC sampler for the Bayesian Gaussian mixture (Section 5.2,
     Algorithm 'gmm'): reweight by the tempering increment, normalise,
@@ -231,12 +256,25 @@ class GmmSampler(_Base):
         if monitor:
             L.smc_monitor(self.ctx, t, self.monitor_out.data_ptr())
 
-    def run(self, alphas, scales=None, monitor: bool = True) -> float:
+    def run(self, alphas, scales=None, monitor: bool = True, adapt: bool = False) -> float:
         """alphas[0..T] with alphas[0] = 0; scales[t] per block or None for
-        the default schedule."""
+        the default schedule.  With adapt, each step's scales are the base
+        scales times the BlockAdapter factors (the host reads the previous
+        step's acceptance counts, one synchronisation per step); the scales
+        used are kept in self.scales_used[T + 1][3]."""
         self.init(monitor)
-        for t in range(1, len(alphas)):
-            self.step(t, float(alphas[t]), None if scales is None else scales[t], monitor)
+        T = len(alphas) - 1
+        base = np.array([(rw_scales if self.move == "rw" else mala_scales)(
+            min(max(float(a), 0.0), 1.0)) for a in alphas]) if scales is None \
+            else np.asarray(scales, dtype=np.float64).reshape(T + 1, 3)
+        used = base.copy()
+        ad = BlockAdapter(self.move) if adapt else None
+        for t in range(1, T + 1):
+            self.step(t, float(alphas[t]), used[t], monitor)
+            if ad is not None and t < T:
+                acc = self.history_host()[t, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3]
+                used[t + 1] = base[t + 1] * ad.update(acc, self.n)
+        self.scales_used = used
         return self.log_z()
 
     def log_z_path(self) -> float:

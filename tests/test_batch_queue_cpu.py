@@ -12,7 +12,7 @@ import pytest
 
 import synth
 
-IT_PF_MOVE, IT_GMM_REWEIGHT, IT_FINAL, IT_RESAMPLE, IT_GMM_STEP = range(5)
+IT_PF_MOVE, IT_GMM_REWEIGHT, IT_FINAL, IT_RESAMPLE, IT_GMM_STEP, IT_MONITOR = range(6)
 
 
 @pytest.fixture(scope="module")
@@ -51,13 +51,15 @@ def _deps(items, shapes):
     """Per item: (counter kind, problem, target per step) it waits for, or None."""
     tiles = [math.ceil(n / 1024) for _, n, _, _ in shapes]
     out = []
-    for kind, p, _, _ in items:
+    for kind, p, _, cnt in items:
         if kind == IT_FINAL:
             out.append(("a", p, tiles[p]))
         elif kind == IT_RESAMPLE:
             out.append(("f", p, 1))
         elif kind == IT_GMM_STEP:
             out.append(("r", p, tiles[p]))
+        elif kind == IT_MONITOR:
+            out.append(("m", p, cnt))
         else:
             out.append(None)
     return out
@@ -72,6 +74,8 @@ def _releases(items, shapes):
             out.append(("f", p))
         elif kind == IT_RESAMPLE and shapes[p][0] == "gmm":
             out.append(("r", p))
+        elif kind == IT_GMM_STEP:
+            out.append(("m", p))
         else:
             out.append(None)
     return out
@@ -96,8 +100,9 @@ def test_queue_covers_every_tile_once_in_dependency_order(L, order, per_item, wh
             covered = sorted(t + q for t, c in seen[(IT_GMM_STEP, p)] for q in range(c))
             assert covered == list(range(math.ceil(n / 64)))
             assert all(1 <= c <= per_item for _, c in seen[(IT_GMM_STEP, p)])
+            assert seen[(IT_MONITOR, p)] == [(0, len(seen[(IT_GMM_STEP, p)]))]
         else:
-            assert (IT_GMM_STEP, p) not in seen
+            assert (IT_GMM_STEP, p) not in seen and (IT_MONITOR, p) not in seen
     # every item after everything it waits for
     pos = {}
     for k, (kind, p, tile, cnt) in enumerate(items):
@@ -110,6 +115,8 @@ def test_queue_covers_every_tile_once_in_dependency_order(L, order, per_item, wh
             assert pos[(IT_FINAL, p)][0] < k
         elif kind == IT_GMM_STEP:
             assert max(pos[(IT_RESAMPLE, p)]) < k
+        elif kind == IT_MONITOR:
+            assert max(pos[(IT_GMM_STEP, p)]) < k
 
 
 def _simulate(items, shapes, G, steps, seed):
@@ -179,6 +186,7 @@ def test_step_model_completes_for_any_grid(L, G, order):
         assert ctr[("a", p)] == steps * nt and ctr[("f", p)] == steps
         if kind == "gmm":
             assert ctr[("r", p)] == steps * nt
+            assert ctr[("m", p)] == steps * math.ceil(math.ceil(n / 64) / 2)
 
 
 def test_unsupported_shapes_are_refused(L):

@@ -87,10 +87,12 @@ def test_batch_matches_oracle(lib, orc, move):
         else:
             sched = pkg.batch.gmm_schedule(kw["alphas"], None, move)
             logz_o, hist_o, pop_o, _ = orc.gmm_run(cfg, kw["y"], sched[:, 0], sched[:, 1:])
-            # exact decisions and 1e-12 agreement up to the first step whose
-            # decisions the oracle records inside a boundary window
+            # exact decisions and 1e-12 agreement (the path-sampling U_t and
+            # trapezoid included) up to the first step whose decisions the
+            # oracle records inside a boundary window
             ts = assert_gmm_run_matches(h[:steps + 1], hist_o, sched[:, 0], L,
-                                        "problem %d" % i, path=False)
+                                        "problem %d" % i)
+            assert br.log_z_path(i) == h[steps, L.SMC_H_PS]
             assert ts == steps + 1, (i, ts)
             D = 3 * kw["K"] - 1
             st = br.state(i).cpu().numpy()[:D]
@@ -126,10 +128,10 @@ def test_batch_equals_single_problem_runs(lib, orc):
             _, hist_o, _, _ = orc.gmm_run(_orc_cfg(orc, kind, kw, "mala"), kw["y"], sched[:, 0],
                                           sched[:, 1:])
             ts = assert_gmm_run_matches(h[:steps + 1], hist_o, sched[:, 0], L,
-                                        "batch problem %d" % i, path=False)
+                                        "batch problem %d" % i)
             assert ts == steps + 1, (i, ts)
             assert_gmm_run_matches(hs[:steps + 1], hist_o, sched[:, 0], L,
-                                   "single problem %d" % i, path=False)
+                                   "single problem %d" % i)
 
 
 def test_graph_replays_equal_eager_steps(lib):
@@ -275,7 +277,7 @@ def test_batch_variants_match_oracle(lib, orc):
                           sweeps=sweeps, scheme=scheme)
         logz_o, hist_o, pop_o, _ = orc.gmm_run(cfg, kw["y"], sched[:, 0], sched[:, 1:])
         ts = assert_gmm_run_matches(br.history_host(i)[:steps + 1], hist_o, sched[:, 0], L,
-                                    "problem %d" % i, path=False)
+                                    "problem %d" % i)
         assert ts == steps + 1, (i, ts)
         D = 3 * kw["K"] - 1
         st = br.state(i).cpu().numpy()[:D]

@@ -438,3 +438,29 @@ def test_monitor_all_rows_against_oracle(lib, orc, K):
         ref = orc.weighted_mean(x, lw)
         assert_close_l1(est, ref, np.abs(x).mean(axis=1) + 1.0, 1e-11, "monitor K=%d t=%d" % (K, t))
     s.check()
+
+
+@pytest.mark.parametrize("move", ["mala", "rw"])
+def test_adaptive_steps_match_oracle_replay(lib, orc, move):
+    # block scales that follow the acceptance rates are host logic over the
+    # GPU's own accept counts: the oracle, given the scales the run used,
+    # reproduces the whole run (decisions exact, values within 1e-12)
+    pkg, L = lib
+    K, n, nd, T = 4, 3000, 120, 14
+    y = synth.gmm_data_four_components(nd, 21)
+    alphas = synth.prior_tempering(T, 2.0)
+    s = pkg.GmmSampler(n, y, K, T, seed=31, move=move)
+    s.run(alphas, adapt=True)
+    used = s.scales_used
+    base = np.array([(pkg.rw_scales if move == "rw" else pkg.mala_scales)(a) for a in alphas])
+    assert not np.allclose(used[2:], base[2:])          # the factors moved
+    hist = s.history_host()
+    _, hist_o, pop_o, _ = orc.gmm_run(orc.gmm_cfg(n, 31, K, move=move), y, alphas, used)
+    ts = assert_gmm_run_matches(hist, hist_o, alphas, L, "adaptive %s" % move)
+    assert ts == T + 1
+    # the factors follow the rule from the recorded accept counts
+    ad = pkg.BlockAdapter(move)
+    for t in range(1, T):
+        f = ad.update(hist[t, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3], n)
+        assert np.allclose(used[t + 1], base[t + 1] * f, rtol=1e-15, atol=0)
+    s.check()
