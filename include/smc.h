@@ -437,13 +437,16 @@ smc_status smc_batch_destroy(smc_batch *b);
  * capture again) afterwards. */
 smc_status smc_batch_autotune(smc_batch *b, int32_t repeats, const char *cache_path);
 /* The step's schedule: out[5] = {queue order, tiles per Metropolis item,
- * workgroups per compute unit, workgroups of the launch, items per step}. */
+ * workgroups per compute unit, workgroups of the launch (workgroups per
+ * compute unit times the compute units, at most the items per step), items
+ * per step}. */
 smc_status smc_batch_schedule(const smc_batch *b, int32_t *out);
 /* Sets the step's schedule without measuring: queue order (0, 1), tiles per
  * Metropolis item (1, 2), workgroups per compute unit (clamped to the
- * occupancy limit).  Results do not depend on the schedule.  Copies the new
- * queue to the device (synchronously) and drops a captured graph; not to be
- * called while the stream is being captured. */
+ * occupancy limit).  Results do not depend on the schedule, and a run may
+ * change it between steps (the steps taken keep their indices).  Copies the
+ * new queue to the device (synchronously) and drops a captured graph; not to
+ * be called while the stream is being captured. */
 smc_status smc_batch_set_schedule(smc_batch *b, int32_t order, int32_t per_item,
                                   int32_t wgs_per_cu);
 /* Waves per 64-particle tile of the initialisation of the mixture samplers

@@ -176,11 +176,19 @@ hipError_t set_schedule(smc_batch *b, int32_t order, int32_t per_item, int32_t w
         e = hipMemcpy(b->queue, q.data(), sizeof(QItem) * q.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess)
         return e;
+    const uint32_t old_per_step = b->nitems + b->nwg;
     b->order = order;
     b->per_item = per_item;
     b->wgs_per_cu = std::max(1, std::min(wgs_per_cu, b->max_wgs_per_cu));
     b->nitems = (uint32_t)q.size();
-    b->nwg = (uint32_t)(b->wgs_per_cu * b->cus);
+    // no more workgroups than the step has items (a small batch's launch
+    // then costs what its few tiles need)
+    b->nwg = std::max(1u, std::min((uint32_t)(b->wgs_per_cu * b->cus), b->nitems));
+    // steps already taken keep their index under the new ticket count
+    if (b->initialised && old_per_step != b->nitems + b->nwg)
+        e = launch_batch_ticket_rebase(b->sync, old_per_step, b->nitems + b->nwg, b->stream);
+    if (e != hipSuccess)
+        return e;
     if (b->exec) {  // a captured step used the old schedule
         (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;

@@ -27,14 +27,16 @@ struct QItem {
     int32_t prob;
     int32_t tile;   // 1024-particle tile (A, R), 64-particle tile (M); 0 for F
     int32_t count;  // M: consecutive 64-particle tiles of the item; monitor: the
-                    // problem's M items per step; 1 otherwise
+                    // problem's 64-particle tiles; 1 otherwise
 };
 
 // Per-problem completion counters (uint32 each, DEP_STRIDE per problem):
 // DEP_A counts finished A tiles, DEP_F finished normalisations, DEP_R
-// finished resampling tiles of mixture samplers, DEP_M their finished
-// Metropolis items.  At step t the targets are t * tiles (A, R), t (F) and
-// t * M items (the monitor).
+// finished resampling tiles of mixture samplers, DEP_M the 64-particle tiles
+// of their finished Metropolis items (an item adds its tile count, so the
+// targets do not depend on the item size a schedule chooses).  At step t the
+// targets are t * tiles (A, R), t (F) and t * 64-particle tiles (the
+// monitor).
 enum : int { DEP_A = 0, DEP_F = 1, DEP_R = 2, DEP_M = 3, DEP_STRIDE = 4 };
 // Launch-wide words: the ticket counter and the abort flag.
 enum : int { SYNC_TICKET = 0, SYNC_ABORT = 1, SYNC_WORDS = 64 };
@@ -92,8 +94,7 @@ inline std::vector<QItem> build_queue(const std::vector<QProblem> &pr, int32_t o
     };
     auto phase_mon = [&](const std::vector<int> &ps) {
         for (int p : ps)
-            q.push_back(QItem{IT_MONITOR, p, 0,
-                              (int32_t)((pr[p].tiles64 + per_item - 1) / per_item)});
+            q.push_back(QItem{IT_MONITOR, p, 0, (int32_t)pr[p].tiles64});
     };
     if (order == ORDER_PHASES) {
         std::vector<int> all(np);

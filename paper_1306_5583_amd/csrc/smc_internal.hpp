@@ -224,6 +224,8 @@ int batch_step_blocks_per_cu();
 hipError_t launch_batch_step(const Prob *probs, const QItem *queue, uint32_t nitems,
                              uint32_t nwg, uint32_t *sync, uint32_t *deps, hipStream_t s);
 hipError_t launch_batch_sync_reset(uint32_t *sync, uint32_t *deps, int64_t nprob, hipStream_t s);
+hipError_t launch_batch_ticket_rebase(uint32_t *sync, uint32_t old_per_step,
+                                      uint32_t new_per_step, hipStream_t s);
 hipError_t launch_batch_monitor0(const Prob *probs, int32_t nprob, hipStream_t s);
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -220,6 +220,7 @@ __global__ __launch_bounds__(TPB, 2) void batch_step_kernel(const Prob *__restri
         if (!sh_go)
             continue;  // aborted: the remaining tickets are drained without work
         int release = -1;
+        uint32_t units = 1;  // what the item adds to its counter
         switch (it.kind) {
         case IT_PF_MOVE: {
             const int32_t obs = t < P.n_data ? t : (int32_t)P.n_data - 1;
@@ -273,6 +274,7 @@ __global__ __launch_bounds__(TPB, 2) void batch_step_kernel(const Prob *__restri
         case IT_GMM_STEP:
             gmm_item_dispatch(P, it.tile, it.count, t, gred, gstash);
             release = DEP_M;
+            units = (uint32_t)it.count;
             break;
         case IT_MONITOR:
             gmm_path_monitor(P, t);
@@ -282,7 +284,8 @@ __global__ __launch_bounds__(TPB, 2) void batch_step_kernel(const Prob *__restri
         }
         __syncthreads();  // every wave's stores of the item are done
         if (release >= 0 && tid == 0)
-            __hip_atomic_fetch_add(dc + release, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(dc + release, units, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -301,6 +304,24 @@ __global__ void batch_sync_reset_kernel(uint32_t *sync, uint32_t *deps, int64_t 
         deps[k] = 0u;
     if (threadIdx.x < SYNC_WORDS)
         sync[threadIdx.x] = 0u;
+}
+
+// A new schedule changes the tickets a step consumes (items + workgroups);
+// the steps already taken keep their count, so the next ticket is rebased
+// to steps * new_per_step (no step in flight).
+__global__ void batch_ticket_rebase_kernel(uint32_t *sync, uint32_t old_per_step,
+                                           uint32_t new_per_step)
+{
+    if (threadIdx.x == 0)
+        sync[SYNC_TICKET] = sync[SYNC_TICKET] / old_per_step * new_per_step;
+}
+
+hipError_t launch_batch_ticket_rebase(uint32_t *sync, uint32_t old_per_step,
+                                      uint32_t new_per_step, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_ticket_rebase_kernel, dim3(1), dim3(WAVE), 0, s, sync, old_per_step,
+                       new_per_step);
+    return hipGetLastError();
 }
 
 int batch_step_blocks_per_cu()

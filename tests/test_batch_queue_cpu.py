@@ -66,18 +66,30 @@ def _deps(items, shapes):
 
 
 def _releases(items, shapes):
+    """Per item: (counter kind, problem, amount) it adds when done, or None
+    (a Metropolis item adds its 64-particle tiles)."""
     out = []
-    for kind, p, _, _ in items:
+    for kind, p, _, cnt in items:
         if kind in (IT_PF_MOVE, IT_GMM_REWEIGHT):
-            out.append(("a", p))
+            out.append(("a", p, 1))
         elif kind == IT_FINAL:
-            out.append(("f", p))
+            out.append(("f", p, 1))
         elif kind == IT_RESAMPLE and shapes[p][0] == "gmm":
-            out.append(("r", p))
+            out.append(("r", p, 1))
         elif kind == IT_GMM_STEP:
-            out.append(("m", p))
+            out.append(("m", p, cnt))
         else:
             out.append(None)
+    return out
+
+
+def _full(shapes):
+    """Units of each counter one step of a problem completes."""
+    out = {}
+    for p, (kind, n, _, _) in enumerate(shapes):
+        out[("a", p)] = out[("r", p)] = math.ceil(n / 1024)
+        out[("f", p)] = 1
+        out[("m", p)] = math.ceil(n / 64)
     return out
 
 
@@ -100,7 +112,8 @@ def test_queue_covers_every_tile_once_in_dependency_order(L, order, per_item, wh
             covered = sorted(t + q for t, c in seen[(IT_GMM_STEP, p)] for q in range(c))
             assert covered == list(range(math.ceil(n / 64)))
             assert all(1 <= c <= per_item for _, c in seen[(IT_GMM_STEP, p)])
-            assert seen[(IT_MONITOR, p)] == [(0, len(seen[(IT_GMM_STEP, p)]))]
+            # the monitor waits for the step's 64-particle tiles, whatever the item size
+            assert seen[(IT_MONITOR, p)] == [(0, math.ceil(n / 64))]
         else:
             assert (IT_GMM_STEP, p) not in seen and (IT_MONITOR, p) not in seen
     # every item after everything it waits for
@@ -119,17 +132,21 @@ def test_queue_covers_every_tile_once_in_dependency_order(L, order, per_item, wh
             assert max(pos[(IT_GMM_STEP, p)]) < k
 
 
-def _simulate(items, shapes, G, steps, seed):
+def _simulate(items, shapes, G, steps, seed, first_step=1, ctr=None, ticket=0):
     """Event-driven model of the step kernel: G workgroups, each taking the
     next ticket when free; ticket -> (step, item) as in the kernel; an item
-    waits until its counter reaches step * target; random durations."""
+    waits until its counter reaches step * target; random durations.  Each
+    item that starts is also checked against what has really finished: every
+    unit of the step it depends on (so a counter target that does not match
+    the releases fails here).  Returns the counters and the next ticket."""
     rng = np.random.default_rng(seed)
     deps, rel = _deps(items, shapes), _releases(items, shapes)
+    full = _full(shapes)
     per_step = len(items) + G
-    ctr = {}
-    ticket = 0
-    for step in range(1, steps + 1):
+    ctr = dict(ctr or {})
+    for step in range(first_step, first_step + steps):
         # one launch: every workgroup loops until it draws a ticket past the items
+        done = {}                                     # units finished in this step
         clock = 0.0
         ready = [(0.0, w) for w in range(G)]          # (time free, workgroup)
         heapq.heapify(ready)
@@ -155,6 +172,9 @@ def _simulate(items, shapes, G, steps, seed):
             for w, k in waiting:
                 d = deps[k]
                 if d is None or ctr.get((d[0], d[1]), 0) >= step * d[2]:
+                    if d is not None:
+                        assert done.get((d[0], d[1]), 0) == full[(d[0], d[1])], \
+                            ("started before its dependency finished", step, items[k])
                     running.append((clock + rng.exponential(1.0), w, k))
                     progressed = True
                 else:
@@ -165,13 +185,15 @@ def _simulate(items, shapes, G, steps, seed):
                 fin, w, k = running.pop(0)
                 clock = max(clock, fin)
                 if rel[k] is not None:
-                    ctr[rel[k]] = ctr.get(rel[k], 0) + 1
+                    c, p, amount = rel[k]
+                    ctr[(c, p)] = ctr.get((c, p), 0) + amount
+                    done[(c, p)] = done.get((c, p), 0) + amount
                 heapq.heappush(ready, (clock, w))
                 progressed = True
             assert progressed, "deadlock: every workgroup waits"
         assert not waiting and not running
-        assert ticket == step * per_step
-    return ctr
+        assert ticket % per_step == 0
+    return ctr, ticket
 
 
 @pytest.mark.parametrize("G", [1, 2, 7, 64, 600])
@@ -180,13 +202,30 @@ def test_step_model_completes_for_any_grid(L, G, order):
     shapes = _shapes_small()
     items = L.smc_batch_plan_queue(_problems(L, shapes), order, 2)
     steps = 3
-    ctr = _simulate([tuple(r) for r in items], shapes, G, steps, seed=G)
+    ctr, _ = _simulate([tuple(r) for r in items], shapes, G, steps, seed=G)
     for p, (kind, n, K, nd) in enumerate(shapes):
         nt = math.ceil(n / 1024)
         assert ctr[("a", p)] == steps * nt and ctr[("f", p)] == steps
         if kind == "gmm":
             assert ctr[("r", p)] == steps * nt
-            assert ctr[("m", p)] == steps * math.ceil(math.ceil(n / 64) / 2)
+            assert ctr[("m", p)] == steps * math.ceil(n / 64)
+
+
+def test_schedule_change_between_steps(L):
+    # two steps on one schedule, then another queue order, item size and
+    # grid: the ticket counter is rebased to steps * new tickets per step
+    # (as the library does) and every wait still follows its dependency
+    shapes = _shapes_small()
+    probs = _problems(L, shapes)
+    qa = [tuple(int(x) for x in r) for r in L.smc_batch_plan_queue(probs, 0, 1)]
+    qb = [tuple(int(x) for x in r) for r in L.smc_batch_plan_queue(probs, 1, 2)]
+    ga, gb = 7, 3
+    ctr, ticket = _simulate(qa, shapes, ga, 2, seed=5)
+    ticket = ticket // (len(qa) + ga) * (len(qb) + gb)
+    ctr, ticket = _simulate(qb, shapes, gb, 2, seed=6, first_step=3, ctr=ctr, ticket=ticket)
+    for p, (kind, n, K, nd) in enumerate(shapes):
+        if kind == "gmm":
+            assert ctr[("m", p)] == 4 * math.ceil(n / 64)
 
 
 def test_unsupported_shapes_are_refused(L):

@@ -187,7 +187,11 @@ def test_autotune_and_cache(lib, tmp_path):
     sch = br.schedule()
     _say("tuned schedule", sch)
     assert sch["order"] in (0, 1) and sch["per_item"] in (1, 2) and sch["wgs_per_cu"] >= 1
-    assert sch["workgroups"] >= 256 * sch["wgs_per_cu"] // 2
+    # the grid: workgroups per compute unit times the compute units, but no
+    # more workgroups than the step has items
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert sch["workgroups"] == min(sch["wgs_per_cu"] * cus, sch["items"]), (sch, cus)
     lines = open(cache).read().strip().splitlines()
     assert len(lines) == 1 and "order=%d per_item=%d wgs_per_cu=%d" % (
         sch["order"], sch["per_item"], sch["wgs_per_cu"]) in lines[0]
@@ -226,6 +230,47 @@ def test_every_schedule_gives_the_same_bits(lib):
                 assert np.array_equal(h0, h1), (order, per_item, wgs, i)
                 assert np.array_equal(x0, x1), (order, per_item, wgs, i)
         br.close()
+
+
+def test_schedule_change_mid_run_keeps_the_bits(lib):
+    # a new schedule changes the tickets a step consumes; the steps taken
+    # before it keep their indices, so the run continues exactly
+    pkg, L = lib
+    steps = 4
+    work = _small_workload(steps)
+    ref = pkg.BatchRunner(_specs(pkg, work))
+    ref.run(steps, graph=False)
+    ref.check()
+    want = [(ref.history_host(i).copy(), ref.state(i).cpu().numpy().copy())
+            for i in range(len(work))]
+    ref.close()
+    br = pkg.BatchRunner(_specs(pkg, work))
+    br.set_schedule(0, 1, 2)
+    br.init()
+    br.step()
+    br.step()
+    br.set_schedule(1, 2, 1)   # other queue order, item size and grid
+    _say("schedule after the change", br.schedule())
+    br.step()
+    br.capture()               # and the rest as graph replays
+    br.replay()
+    br.check()
+    for i, (h0, x0) in enumerate(want):
+        assert np.array_equal(h0, br.history_host(i)), i
+        assert np.array_equal(x0, br.state(i).cpu().numpy()), i
+    br.close()
+
+
+def test_small_batch_grid_is_capped_at_its_items(lib):
+    # one small filter: the launch has no more workgroups than items
+    pkg, L = lib
+    work = _small_workload(2)
+    br = pkg.BatchRunner(_specs(pkg, work[:1]))
+    sch = br.schedule()
+    assert sch["workgroups"] <= sch["items"], sch
+    br.run(2, graph=True)
+    br.check()
+    br.close()
 
 
 def test_batch_variants_match_oracle(lib, orc):
