@@ -30,6 +30,17 @@ namespace smc {
 constexpr double kHalfLog2Pi = 0.91893853320467274178032973640562;
 constexpr int GMM_MAXW = 8;       // waves per particle tile
 constexpr int GMM_RED_GROUP = 4;  // accumulators combined per LDS round
+// Where a Metropolis block reads and writes the particles' state: global
+// memory both ways (each block its own launch or queue item) or, when one
+// workgroup runs a step's blocks in sequence, global -> LDS for the first,
+// LDS -> LDS between blocks and LDS -> global for the last.
+constexpr int GMM_IO_GLOBAL = 0, GMM_IO_FIRST = 1, GMM_IO_LDS = 2, GMM_IO_LAST = 3;
+// doubles of the LDS state copy of one 64-particle tile: D coordinates, the
+// log-likelihood, the log prior and, for MALA, the D-gradient
+constexpr int gmm_hand_doubles(int K, bool mala)
+{
+    return (mala ? 2 * (3 * K - 1) + 2 : 3 * K + 1) * WAVE;
+}
 
 
 // log omega_j (j = 0..K-1) from the K-1 logits, reference component K.
@@ -454,17 +465,23 @@ constexpr int GMM_RED_DOUBLES = GMM_RED_GROUP * GMM_MAXW * WAVE;
 template <int K, bool MALA>
 constexpr int gmm_stash_doubles() { return BlockStash<K, MALA>::ROWS * WAVE; }
 
-// `red` (GMM_RED_DOUBLES) and `stash` (gmm_stash_doubles<K, MALA>()) are the
-// caller's LDS.
+// `red` (GMM_RED_DOUBLES), `stash` (gmm_stash_doubles<K, MALA>()) and, for
+// the LDS hand-off modes `io`, `hand` (gmm_hand_doubles(K, MALA)) are the
+// caller's LDS.  With GMM_IO_GLOBAL the block reads `src` and writes `dst`
+// (every row when `full`, else the accepted rows in place).
 template <int K, bool MALA>
 __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__restrict__ src,
                                                double *__restrict__ dst, int full, int W,
                                                int64_t tile, uint32_t t, int block, int sweep,
                                                double alpha, double scale, int32_t step,
-                                               double *red, double *stash)
+                                               double *red, double *stash, int io = GMM_IO_GLOBAL,
+                                               double *hand = nullptr)
 {
     constexpr int D = 3 * K - 1;
     using S = BlockStash<K, MALA>;
+    const bool in_lds = io == GMM_IO_LDS || io == GMM_IO_LAST;
+    const bool out_lds = io == GMM_IO_FIRST || io == GMM_IO_LDS;
+    const bool out_all = full || io != GMM_IO_GLOBAL;
     const int32_t *__restrict__ anc = P.anc;
     const int64_t n = P.n, nd = P.n_data;
     const double *__restrict__ y = P.data;
@@ -473,11 +490,19 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
     const GmmPrior pr = P.prior;
     double *__restrict__ hist = P.hist;
     const int64_t hist_len = P.hist_len;
-    const bool gather = full && P.scalars[SMC_S_RESAMPLED] != 0.0;
+    const bool gather = full && !in_lds && P.scalars[SMC_S_RESAMPLED] != 0.0;
     const int lane = lane_id();
     const int64_t i = tile * WAVE + lane;
     const bool valid = i < n;
-    const int64_t si = valid ? (gather ? (int64_t)anc[i] : i) : 0;
+    // the state is read from column si of rows of length sn (global: the
+    // particle or its ancestor; LDS: the lane) and written to column wi of
+    // rows of length wn
+    const int64_t si = in_lds ? lane : (valid ? (gather ? (int64_t)anc[i] : i) : 0);
+    const int64_t sn = in_lds ? WAVE : n;
+    const double *__restrict__ rs = in_lds ? hand : src;
+    double *__restrict__ ws = out_lds ? hand : dst;
+    const int64_t wi = out_lds ? lane : i;
+    const int64_t wn = out_lds ? WAVE : n;
     const uint32_t ii = (uint32_t)(valid ? i : 0);
     const int off = block * K;
     const int dim = block == 2 ? K - 1 : K;
@@ -485,7 +510,7 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
     MixLik<K, MALA> L;
     {
         Proposal<K, MALA> Q;
-        Q.build(src, n, si, ii, key, t, p, block, sweep, alpha, scale, pr);
+        Q.build(rs, sn, si, ii, key, t, p, block, sweep, alpha, scale, pr);
         double logw[K];
         log_weights<K>(Q.prop, logw);
         L.setup(Q.prop, logw);
@@ -515,8 +540,8 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
     L.chunk(y, k0, k1);
     double ll0 = 0.0, lp0 = 0.0;
     if (wave_id() == 0) {
-        ll0 = src[(int64_t)D * n + si];
-        lp0 = src[(int64_t)(D + 1) * n + si];
+        ll0 = rs[(int64_t)D * sn + si];
+        lp0 = rs[(int64_t)(D + 1) * sn + si];
     }
     combine_waves<K, MALA>(L, W, red);
     if (wave_id() != 0)
@@ -524,7 +549,7 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
     double phi[D > 0 ? D : 1];
 #pragma unroll
     for (int q = 0; q < D; ++q)
-        phi[q] = src[(int64_t)q * n + si];
+        phi[q] = rs[(int64_t)q * sn + si];
     const double lpp = stash[S::LPP * WAVE + lane];
     const double cur = alpha == 0.0 ? lp0 : lp0 + alpha * ll0;
     double logr = (alpha == 0.0 ? lpp : lpp + alpha * L.ll) - cur;
@@ -552,36 +577,36 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
         logr += (stash[S::FWD * WAVE + lane] - bwd) / (2.0 * h2);
     }
     const bool acc = valid && stash[S::LOGU * WAVE + lane] <= logr;
-    if (valid) {
-        if (full) {
+    if (valid || out_lds) {
+        if (out_all) {
 #pragma unroll
             for (int q = 0; q < D; ++q) {
                 const int mm = q - off;
                 const bool inb = mm >= 0 && mm < dim;
-                dst[(int64_t)q * n + i] =
+                ws[(int64_t)q * wn + wi] =
                     (acc && inb) ? stash[(S::PROP + (inb ? mm : 0)) * WAVE + lane] : phi[q];
             }
-            dst[(int64_t)D * n + i] = acc ? L.ll : ll0;
-            dst[(int64_t)(D + 1) * n + i] = acc ? lpp : lp0;
+            ws[(int64_t)D * wn + wi] = acc ? L.ll : ll0;
+            ws[(int64_t)(D + 1) * wn + wi] = acc ? lpp : lp0;
             if (MALA) {
 #pragma unroll
                 for (int q = 0; q < D; ++q)
-                    dst[(int64_t)(D + 2 + q) * n + i] =
-                        acc ? gnew[q] : src[(int64_t)(D + 2 + q) * n + si];
+                    ws[(int64_t)(D + 2 + q) * wn + wi] =
+                        acc ? gnew[q] : rs[(int64_t)(D + 2 + q) * sn + si];
             }
         } else if (acc) {
 #pragma unroll
             for (int q = 0; q < D; ++q) {
                 const int mm = q - off;
                 if (mm >= 0 && mm < dim)
-                    dst[(int64_t)q * n + i] = stash[(S::PROP + mm) * WAVE + lane];
+                    ws[(int64_t)q * wn + wi] = stash[(S::PROP + mm) * WAVE + lane];
             }
-            dst[(int64_t)D * n + i] = L.ll;
-            dst[(int64_t)(D + 1) * n + i] = lpp;
+            ws[(int64_t)D * wn + wi] = L.ll;
+            ws[(int64_t)(D + 1) * wn + wi] = lpp;
             if (MALA) {
 #pragma unroll
                 for (int q = 0; q < D; ++q)
-                    dst[(int64_t)(D + 2 + q) * n + i] = gnew[q];
+                    ws[(int64_t)(D + 2 + q) * wn + wi] = gnew[q];
             }
         }
     }
@@ -593,11 +618,11 @@ __device__ __forceinline__ void gmm_block_tile(const Prob &P, const double *__re
 }
 
 // All Metropolis blocks of a step (every sweep) in one launch: the tile's
-// workgroup runs the blocks one after the other, each reading back the state
-// the previous block's wave 0 wrote for the same particles (visible to the
-// workgroup after the barrier).  The first block reads `src` (through the
-// ancestors when the step resampled and `full` is set) and writes `dst`;
-// later blocks update `dst` in place.
+// workgroup runs the blocks one after the other.  The first block reads
+// `src` (through the ancestors when the step resampled and `full` is set)
+// and leaves the tile's state in LDS; each later block reads the state the
+// previous block's wave 0 left there (visible to the workgroup after the
+// barrier), and the last one writes the whole state to `dst`.
 template <int K, bool MALA>
 __global__ __launch_bounds__(GMM_MAXW *WAVE) void gmm_step_kernel(
     Prob P, const double *__restrict__ src, double *__restrict__ dst, int full, int W, uint32_t t,
@@ -605,15 +630,18 @@ __global__ __launch_bounds__(GMM_MAXW *WAVE) void gmm_step_kernel(
 {
     __shared__ double red[GMM_RED_DOUBLES];
     __shared__ double stash[gmm_stash_doubles<K, MALA>()];
+    __shared__ double hand[gmm_hand_doubles(K, MALA)];
     const int nb = K == 1 ? 2 : 3;
     for (int sw = 0; sw < sweeps; ++sw)
         for (int b = 0; b < nb; ++b) {
             const bool first = sw == 0 && b == 0;
+            const bool last = sw == sweeps - 1 && b == nb - 1;
             if (!first)
                 __syncthreads();
-            gmm_block_tile<K, MALA>(P, first ? src : dst, dst, first ? full : 0, W, blockIdx.x,
-                                    t, b, sw, alpha, b == 0 ? s0 : (b == 1 ? s1 : s2), step, red,
-                                    stash);
+            gmm_block_tile<K, MALA>(P, src, dst, first ? full : 0, W, blockIdx.x, t, b, sw, alpha,
+                                    b == 0 ? s0 : (b == 1 ? s1 : s2), step, red, stash,
+                                    first ? GMM_IO_FIRST : (last ? GMM_IO_LAST : GMM_IO_LDS),
+                                    hand);
         }
 }
 
