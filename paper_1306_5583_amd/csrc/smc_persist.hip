@@ -42,8 +42,26 @@ __device__ __forceinline__ uint32_t load_relaxed(const uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread 0 only: waits until *ctr >= target, then acquires.  False on an
-// abort raised elsewhere or on a time-out (which raises it).
+// Publishing an item's results: every wave drains its own stores before
+// the workgroup barrier, then thread 0 writes the L2 back (agent-scope
+// release), waits for the write-back to complete and only then advances the
+// counter.  The waits are explicit: when the releasing wave has no store of
+// its own in flight, the compiler emits the write-back and the atomic
+// back to back, and a workgroup on another XCD could then see the counter
+// before the data reached memory (it read a previous step's tile partials).
+__device__ __forceinline__ void drain_memory() { __builtin_amdgcn_s_waitcnt(0); }
+
+__device__ __forceinline__ void release_add(uint32_t *ctr, uint32_t units)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    drain_memory();
+    __hip_atomic_fetch_add(ctr, units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 only: waits until *ctr >= target, then acquires (the cache
+// invalidation completes before the workgroup barrier that follows, so the
+// other waves' loads cannot overtake it).  False on an abort raised
+// elsewhere or on a time-out (which raises it).
 __device__ bool wait_at_least(const uint32_t *ctr, uint32_t target, uint32_t *abort_flag,
                               int32_t *err_word)
 {
@@ -63,6 +81,7 @@ __device__ bool wait_at_least(const uint32_t *ctr, uint32_t target, uint32_t *ab
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    drain_memory();
     return true;
 }
 
@@ -282,10 +301,10 @@ __global__ __launch_bounds__(TPB, 2) void batch_step_kernel(const Prob *__restri
         default:
             break;
         }
-        __syncthreads();  // every wave's stores of the item are done
+        drain_memory();   // this wave's stores of the item have reached L2
+        __syncthreads();
         if (release >= 0 && tid == 0)
-            __hip_atomic_fetch_add(dc + release, units, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            release_add(dc + release, units);
     }
 }
 

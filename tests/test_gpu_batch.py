@@ -273,6 +273,28 @@ def test_small_batch_grid_is_capped_at_its_items(lib):
     br.close()
 
 
+def test_repeated_runs_are_bit_identical(lib):
+    # many small samplers whose normalisation, resampling and Metropolis
+    # items follow each other closely on different XCDs: a release that
+    # lets a counter overtake its data shows up as runs that differ (a
+    # stale tile partial changed L, the ESS and every later step)
+    pkg, L = lib
+    steps = 60
+    rng = np.random.default_rng(909)
+    probs = [synth.BatchProblem("gmm", 2048, int(rng.integers(1, 1 << 40)),
+                                int(rng.integers(1, 1000)), 3, 120) for _ in range(48)]
+    work = synth.batched_workload(steps, probs)
+    out = []
+    for rep in range(2):
+        br = pkg.BatchRunner(_specs(pkg, work))
+        br.run(steps, graph=True)
+        br.check()
+        out.append([br.history_host(i).copy() for i in range(len(work))])
+        br.close()
+    for i, (h0, h1) in enumerate(zip(*out)):
+        assert np.array_equal(h0, h1), i
+
+
 def test_batch_variants_match_oracle(lib, orc):
     """What the single-problem contexts allow, batched: FP32 filter state,
     stratified resampling for filters and samplers, random-walk and MALA
