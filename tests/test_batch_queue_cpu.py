@@ -42,7 +42,7 @@ def _shapes_small():
             ("gmm", 3333, 5, 130), ("pf", 3001, 0, 0), ("gmm", 700, 2, 45)]
 
 
-def _shapes_c4():
+def _shapes_batched_benchmark():
     # the 128-filter / 32-sampler workload's shapes
     return [(q.kind, q.n_particles, q.K, q.n_data) for q in synth.batched_problems()]
 
@@ -95,9 +95,9 @@ def _full(shapes):
 
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("per_item", [1, 2])
-@pytest.mark.parametrize("which", ["small", "c4"])
+@pytest.mark.parametrize("which", ["small", "benchmark"])
 def test_queue_covers_every_tile_once_in_dependency_order(L, order, per_item, which):
-    shapes = _shapes_small() if which == "small" else _shapes_c4()
+    shapes = _shapes_small() if which == "small" else _shapes_batched_benchmark()
     items = L.smc_batch_plan_queue(_problems(L, shapes), order, per_item)
     seen = {}
     for kind, p, tile, cnt in items:

@@ -302,7 +302,7 @@ def test_gradient_central_differences_c3_shape(lib, orc):
 
 
 def test_lockstep_c2_full_size(lib, orc):
-    # the C2 shape (N = 2^14, K = 4, n = 1000): two steps in lock-step
+    # the random-walk benchmark shape (N = 2^14, K = 4, n = 1000): two steps in lock-step
     _lockstep_gmm(lib, orc, 1 << 14, 4, 1000, 2, "rw", power=1.0)
 
 
