@@ -141,6 +141,11 @@ struct MixLik {
         }
     }
 
+    // FAST (log-likelihood only): the terms' 2^x without the clamp that maps
+    // x = -inf to 0; a non-finite term turns the segment's product into NaN
+    // and chunk() redoes that segment with the clamp, so the results are
+    // those of the clamped form for every input
+    template <bool FAST = false>
     __device__ __forceinline__ void point(double y)
     {
         double e[K], u[K];
@@ -165,7 +170,7 @@ struct MixLik {
         double s = 0.0;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            e[j] = exp2_nonpos(e[j] - m);
+            e[j] = FAST ? exp2_nonpos_finite(e[j] - m) : exp2_nonpos(e[j] - m);
             s = j == 0 ? e[0] : s + e[j];
         }
         m2 += m;
@@ -202,26 +207,48 @@ struct MixLik {
     // the two-point loop the next pair is loaded one iteration ahead
     __device__ __forceinline__ void chunk(const double *__restrict__ y, int64_t k0, int64_t k1)
     {
+        constexpr bool FAST = !GRAD && K > 1;
         int64_t k = k0;
         while (k < k1) {
-            const int64_t kend = min(k + FLUSH, k1);
+            const int64_t kseg = k, kend = min(k + FLUSH, k1);
+            const double m2_seg = m2;
             if (K <= 8) {  // two points per iteration while registers allow
                 if (k + 2 <= kend) {
                     double y0 = y[k], y1 = y[k + 1];
-                    for (; k + 4 <= kend; k += 2) {
-                        const double n0 = y[k + 2], n1 = y[k + 3];
-                        point(y0);
-                        point(y1);
-                        y0 = n0;
-                        y1 = n1;
+                    if constexpr (FAST) {
+                        // unrolled once more: the prefetched pair alternates
+                        // between two register pairs instead of being moved
+#pragma unroll 2
+                        for (; k + 4 <= kend; k += 2) {
+                            const double n0 = y[k + 2], n1 = y[k + 3];
+                            point<true>(y0);
+                            point<true>(y1);
+                            y0 = n0;
+                            y1 = n1;
+                        }
+                    } else {
+                        for (; k + 4 <= kend; k += 2) {
+                            const double n0 = y[k + 2], n1 = y[k + 3];
+                            point(y0);
+                            point(y1);
+                            y0 = n0;
+                            y1 = n1;
+                        }
                     }
-                    point(y0);
-                    point(y1);
+                    point<FAST>(y0);
+                    point<FAST>(y1);
                     k += 2;
                 }
             }
             for (; k < kend; ++k)
-                point(y[k]);
+                point<FAST>(y[k]);
+            if (FAST && !(prod == prod)) {
+                // a non-finite term: the segment again with the clamp
+                m2 = m2_seg;
+                prod = 1.0;
+                for (int64_t q = kseg; q < kend; ++q)
+                    point<false>(y[q]);
+            }
             lsum += log_d(prod);
             prod = 1.0;
         }

@@ -179,6 +179,21 @@ __host__ __device__ inline double exp2_nonpos(double x)
     return ldexp(p, (int)k);
 }
 
+// 2^x for finite x <= 0 without the lower clamp (device code: the
+// exponent conversion saturates): the same value as exp2_nonpos for every
+// finite x, one instruction less; -inf or NaN gives NaN, which a caller
+// detects and redoes with exp2_nonpos.
+__device__ inline double exp2_nonpos_finite(double x)
+{
+    const double k = rint(x);
+    const double r = x - k;  // exact
+    double p = detail::kExp2C[10];
+#pragma unroll
+    for (int j = 9; j >= 0; --j)
+        p = fma(p, r, detail::kExp2C[j]);
+    return ldexp(p, (int)k);
+}
+
 // sin(pi x) and cos(pi x) for |x| < 2^50.
 __host__ __device__ inline void sincospi_d(double x, double *sp, double *cp)
 {

@@ -252,6 +252,38 @@ def test_loglik_grad_entry(lib, orc, K):
         assert_close_l1(g[:, i], gr, np.abs(gr) + 2 * nd, 1e-12, "grad")
 
 
+@pytest.mark.parametrize("K", [2, 4, 6])
+def test_loglik_without_gradient_and_far_components(lib, orc, K):
+    # the likelihood without the gradient takes the terms' 2^x unclamped and
+    # redoes a 64-point segment when a term is not finite: components 1e160
+    # away from every point (u^2 overflows, their terms are 0) in some
+    # columns, ordinary ones in the others; every value against the oracle
+    pkg, L = lib
+    n, nd = 96, 1000
+    y, _ = synth.gmm_data_spaced(nd, K, 2718)
+    rng = np.random.default_rng(100 + K)
+    mu = rng.normal(0, 3, (K, n))
+    eta = rng.normal(0, 0.5, (K, n))
+    z = rng.normal(0, 0.5, (K - 1, n))
+    far = np.arange(n) % 3 == 0
+    mu[0, far] = 1e160                 # one far component in every third column
+    mu[K - 1, np.arange(n) % 6 == 1] = -1e160
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    mu_d, eta_d, z_d, y_d = dev(mu), dev(eta), dev(z), dev(y)
+    ll = torch.zeros(n, dtype=torch.float64, device="cuda")
+    L.smc_gmm_loglik_grad(mu_d.data_ptr(), eta_d.data_ptr(), z_d.data_ptr(), n, K,
+                          y_d.data_ptr(), nd, ll.data_ptr(), 0,
+                          torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    ll = ll.cpu().numpy()
+    assert np.all(np.isfinite(ll))
+    for i in range(n):
+        phi = np.concatenate([mu[:, i], eta[:, i], z[:, i]])
+        v = orc.gmm_loglik(phi, K, y)
+        v = v[0] if isinstance(v, tuple) else v
+        assert_close_l1(ll[i], v, abs(v) + 50, 1e-12, "ll")
+
+
 def test_autograd_function_gradcheck(lib, orc):
     pkg, L = lib
     K, n, nd = 3, 8, 40
