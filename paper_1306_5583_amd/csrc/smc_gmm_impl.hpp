@@ -141,10 +141,8 @@ struct MixLik {
         }
     }
 
-    // FAST (log-likelihood only): the terms' 2^x without the clamp that maps
-    // x = -inf to 0; a non-finite term turns the segment's product into NaN
-    // and chunk() redoes that segment with the clamp, so the results are
-    // those of the clamped form for every input
+    // FAST: the terms' 2^x without the clamp that maps x = -inf to 0 (the
+    // same value for every finite x; see chunk())
     template <bool FAST = false>
     __device__ __forceinline__ void point(double y)
     {
@@ -203,34 +201,46 @@ struct MixLik {
         }
     }
 
-    // accumulate a contiguous chunk of the data with wave-uniform loads; in
-    // the two-point loop the next pair is loaded one iteration ahead
-    __device__ __forceinline__ void chunk(const double *__restrict__ y, int64_t k0, int64_t k1)
+    // the running sums of a chunk back to their start (the constants of
+    // setup() stay)
+    __device__ __forceinline__ void reset()
     {
-        constexpr bool FAST = !GRAD && K > 1;
+        ll = m2 = lsum = 0.0;
+        prod = 1.0;
+        if (GRAD) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                gmu[j] = geta[j] = gr[j] = 0.0;
+        }
+    }
+
+    // the points [k0, k1) in FLUSH-point segments with wave-uniform loads;
+    // in the two-point loop the next pair is loaded one iteration ahead
+    template <bool FAST>
+    __device__ __forceinline__ void run(const double *__restrict__ y, int64_t k0, int64_t k1)
+    {
         int64_t k = k0;
         while (k < k1) {
-            const int64_t kseg = k, kend = min(k + FLUSH, k1);
-            const double m2_seg = m2;
+            const int64_t kend = min(k + FLUSH, k1);
             if (K <= 8) {  // two points per iteration while registers allow
                 if (k + 2 <= kend) {
                     double y0 = y[k], y1 = y[k + 1];
-                    if constexpr (FAST) {
+                    if constexpr (FAST && !GRAD) {
                         // unrolled once more: the prefetched pair alternates
                         // between two register pairs instead of being moved
 #pragma unroll 2
                         for (; k + 4 <= kend; k += 2) {
                             const double n0 = y[k + 2], n1 = y[k + 3];
-                            point<true>(y0);
-                            point<true>(y1);
+                            point<FAST>(y0);
+                            point<FAST>(y1);
                             y0 = n0;
                             y1 = n1;
                         }
                     } else {
                         for (; k + 4 <= kend; k += 2) {
                             const double n0 = y[k + 2], n1 = y[k + 3];
-                            point(y0);
-                            point(y1);
+                            point<FAST>(y0);
+                            point<FAST>(y1);
                             y0 = n0;
                             y1 = n1;
                         }
@@ -242,17 +252,27 @@ struct MixLik {
             }
             for (; k < kend; ++k)
                 point<FAST>(y[k]);
-            if (FAST && !(prod == prod)) {
-                // a non-finite term: the segment again with the clamp
-                m2 = m2_seg;
-                prod = 1.0;
-                for (int64_t q = kseg; q < kend; ++q)
-                    point<false>(y[q]);
-            }
             lsum += log_d(prod);
             prod = 1.0;
         }
         finish();
+    }
+
+    // accumulate a contiguous chunk of the data: first with the terms' 2^x
+    // unclamped; a non-finite term makes the log-likelihood NaN, and then the
+    // chunk is summed again with the clamp, so the results are those of the
+    // clamped form for every input
+    __device__ __forceinline__ void chunk(const double *__restrict__ y, int64_t k0, int64_t k1)
+    {
+        if constexpr (K > 1) {
+            run<true>(y, k0, k1);
+            if (!(ll == ll)) {
+                reset();
+                run<false>(y, k0, k1);
+            }
+        } else {
+            run<false>(y, k0, k1);
+        }
     }
 
     static constexpr int NACC = GRAD ? 1 + 3 * K : 1;
