@@ -252,12 +252,14 @@ def test_loglik_grad_entry(lib, orc, K):
         assert_close_l1(g[:, i], gr, np.abs(gr) + 2 * nd, 1e-12, "grad")
 
 
+@pytest.mark.parametrize("grad", [False, True])
 @pytest.mark.parametrize("K", [2, 4, 6])
-def test_loglik_without_gradient_and_far_components(lib, orc, K):
-    # the likelihood without the gradient takes the terms' 2^x unclamped and
-    # redoes a 64-point segment when a term is not finite: components 1e160
+def test_loglik_far_components(lib, orc, K, grad):
+    # the likelihood loops take the terms' 2^x unclamped and sum a chunk
+    # again with the clamp when a term is not finite: components 1e160
     # away from every point (u^2 overflows, their terms are 0) in some
-    # columns, ordinary ones in the others; every value against the oracle
+    # columns, ordinary ones in the others; every value (and gradient)
+    # against the oracle
     pkg, L = lib
     n, nd = 96, 1000
     y, _ = synth.gmm_data_spaced(nd, K, 2718)
@@ -271,16 +273,25 @@ def test_loglik_without_gradient_and_far_components(lib, orc, K):
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
     mu_d, eta_d, z_d, y_d = dev(mu), dev(eta), dev(z), dev(y)
     ll = torch.zeros(n, dtype=torch.float64, device="cuda")
+    g = torch.zeros((3 * K - 1, n), dtype=torch.float64, device="cuda")
     L.smc_gmm_loglik_grad(mu_d.data_ptr(), eta_d.data_ptr(), z_d.data_ptr(), n, K,
-                          y_d.data_ptr(), nd, ll.data_ptr(), 0,
+                          y_d.data_ptr(), nd, ll.data_ptr(), g.data_ptr() if grad else 0,
                           torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
-    ll = ll.cpu().numpy()
+    ll, g = ll.cpu().numpy(), g.cpu().numpy()
     assert np.all(np.isfinite(ll))
     for i in range(n):
         phi = np.concatenate([mu[:, i], eta[:, i], z[:, i]])
-        v = orc.gmm_loglik(phi, K, y)
-        v = v[0] if isinstance(v, tuple) else v
+        if grad:
+            v, gr = orc.gmm_loglik(phi, K, y, grad=True)
+            # the far component's log-precision derivative is a sum of
+            # r (1/2 - lambda d^2 / 2) with r = 0 exactly and lambda d^2 = inf:
+            # the oracle's literal product gives NaN, the limit is 0
+            bad = ~np.isfinite(gr)
+            assert np.all(g[bad, i] == 0.0), (i, g[bad, i])
+            assert_close_l1(g[~bad, i], gr[~bad], np.abs(gr[~bad]) + 2 * nd, 1e-12, "grad")
+        else:
+            v = orc.gmm_loglik(phi, K, y)
         assert_close_l1(ll[i], v, abs(v) + 50, 1e-12, "ll")
 
 
