@@ -101,9 +101,9 @@ __device__ __forceinline__ double2 normal2(uint4 w)
 {
     const double u1 = u53(w.x, w.y);
     const double u2 = u53(w.z, w.w);
-    const double r = sqrt(-2.0 * log_pos_d(u1));
+    const double r = sqrt_nonneg_d(-2.0 * log_pos_d(u1));
     double s, c;
-    sincospi_d(u2 + u2, &s, &c);
+    sincospi_d<true>(u2 + u2, &s, &c);  // argument in (0, 2]
     return make_double2(r * c, r * s);
 }
 

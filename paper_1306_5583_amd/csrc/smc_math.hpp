@@ -194,7 +194,30 @@ __device__ inline double exp2_nonpos_finite(double x)
     return ldexp(p, (int)k);
 }
 
-// sin(pi x) and cos(pi x) for |x| < 2^50.
+// Square root of a >= 0 that is 0 or at least 2^-767 (device code): the
+// hardware reciprocal square-root estimate refined by one Goldschmidt step
+// and one residual correction, the same operations and rounding as the
+// library square root on that range, without its rescaling of tiny
+// arguments and special-case select (0 is the only special value here).
+__device__ inline double sqrt_nonneg_d(double a)
+{
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y;
+    double h = y * 0.5;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, a);
+    g = fma(d, h, g);
+    const double d2 = fma(-g, g, a);
+    g = fma(d2, h, g);
+    return a == 0.0 ? a : g;  // sqrt(-0) = -0
+}
+
+// sin(pi x) and cos(pi x) for |x| < 2^50 (SMALL: |x| < 2^29, where the
+// quadrant index converts to a 32-bit integer in one instruction; the same
+// values).
+template <bool SMALL = false>
 __host__ __device__ inline void sincospi_d(double x, double *sp, double *cp)
 {
     const double n = rint(x + x);          // nearest multiple of 1/2
@@ -209,7 +232,7 @@ __host__ __device__ inline void sincospi_d(double x, double *sp, double *cp)
         c = detail::fma_k(c, r2, detail::kCosC[k]);
     }
     s *= r;
-    const int q = (int)(long long)n & 3;
+    const int q = (SMALL ? (int)n : (int)(long long)n) & 3;
     const double ss = (q & 1) ? c : s;
     const double cc = (q & 1) ? s : c;
     *sp = (q & 2) ? -ss : ss;
