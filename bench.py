@@ -251,7 +251,7 @@ def _cpu_info():
 
 def _host_threads():
     """Threads for the all-core oracle timing: the CPU share of this process
-    (its affinity mask), at most 16 (a GPU machine's share per GPU)."""
+    (its affinity mask), at most 16 (the host cores one GPU is given)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -260,7 +260,7 @@ def _host_threads():
 
 
 def cpu_baseline_pf(args, fp32=False, scheme=None):
-    """The oracle on the machine's host, on bounded samples of the workload (the
+    """The oracle on the host of the GPU machine, on bounded samples of the workload (the
     first 30 observations): all the process's cores (up to 16) at the full
     particle count, and one thread at N = 2^20.  The oracle runs its
     per-particle loops on the threads and its sums sequentially, so both
