@@ -352,8 +352,11 @@ smc_status smc_draw_words(uint64_t seed, uint32_t step, uint32_t tag, uint32_t c
  * sweeps), of this context are
  * timed (count = 0 disarms).  smc_profile_read waits for them and writes
  * up to `capacity` durations in milliseconds, in launch order; *written
- * receives how many.  Host-side bookkeeping only; events are owned by the
- * context. */
+ * receives how many.  The events are timing-only: created without the
+ * system-scope fence, so a timed launch ends with the same device-scope
+ * release as an untimed one (a system-scope release would add a write-back
+ * of the L2 to the measured duration).  Host-side bookkeeping only; events
+ * are owned by the context. */
 smc_status smc_profile_start(smc_ctx *ctx, int32_t count);
 smc_status smc_profile_read(smc_ctx *ctx, float *ms, int32_t capacity, int32_t *written);
 

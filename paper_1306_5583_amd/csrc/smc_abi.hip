@@ -402,7 +402,8 @@ smc_status smc_profile_start(smc_ctx *ctx, int32_t count)
     drop_profile_events(c);
     c.prof_ev.resize(2 * (size_t)count, nullptr);
     for (int32_t k = 0; k < 2 * count; ++k) {
-        const hipError_t e = hipEventCreate(&c.prof_ev[k]);
+        // timing only: no system-scope fence at the end of the timed launch
+        const hipError_t e = hipEventCreateWithFlags(&c.prof_ev[k], hipEventDisableSystemFence);
         if (e != hipSuccess) {
             c.prof_ev.resize(k);
             drop_profile_events(c);
