@@ -464,7 +464,11 @@ smc_status smc_batch_init(smc_batch *b);
  * the previous step's monitor), mixture samplers reweight; all normalise
  * and resample if their ESS is low; mixture samplers then run their
  * Metropolis blocks.  SMC_ERR_BAD_STATE before smc_batch_init or when a
- * problem has no observation / schedule / history row left. */
+ * problem has no observation / schedule / history row left;
+ * SMC_ERR_UNSUPPORTED past the step that the 32-bit ticket and completion
+ * counters can index: step t needs t * (work items + workgroups of the
+ * step) < 2^32 and t * (tiles of the largest problem: 1024-particle tiles
+ * of a filter, 64-particle tiles of a mixture sampler) < 2^32. */
 smc_status smc_batch_step(smc_batch *b);
 /* Captures one step into a HIP graph (replaces a previous capture); the
  * step index comes from the device, so one capture serves every step. */

@@ -55,6 +55,8 @@ struct smc_batch {
     bool initialised = false;
     int host_step = 0;
     int max_steps = 0;
+    int64_t max_count = 1;          // largest per-step counter target unit (tiles per problem)
+    int counter_steps = 0;          // steps the 32-bit ticket and counters can index
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::string last_error;
@@ -184,6 +186,16 @@ hipError_t set_schedule(smc_batch *b, int32_t order, int32_t per_item, int32_t w
     // no more workgroups than the step has items (a small batch's launch
     // then costs what its few tiles need)
     b->nwg = std::max(1u, std::min((uint32_t)(b->wgs_per_cu * b->cus), b->nitems));
+    // The ticket and the completion counters are 32-bit and only grow: step t
+    // takes tickets up to t * (items + workgroups) and waits for counter
+    // targets up to t * (tiles of the largest problem), so the step index is
+    // capped where either would wrap.
+    {
+        const uint64_t per = (uint64_t)b->nitems + b->nwg;
+        const uint64_t lim = std::min<uint64_t>(0xFFFFFFFFull / per,
+                                                0xFFFFFFFFull / (uint64_t)b->max_count);
+        b->counter_steps = (int)std::min<uint64_t>(lim, (uint64_t)INT_MAX);
+    }
     // steps already taken keep their index under the new ticket count
     if (b->initialised && old_per_step != b->nitems + b->nwg)
         e = launch_batch_ticket_rebase(b->sync, old_per_step, b->nitems + b->nwg, b->stream);
@@ -343,6 +355,11 @@ smc_status smc_batch_create(const smc_batch_problem *probs, int32_t nprob, void 
         P.sched = q.schedule;
         b->P.push_back(P);
         const int64_t nt = ceil_div(q.cfg.n, TILE);
+        // counter targets per step: tiles (move, reweight, resampling), and
+        // for a mixture sampler its 64-particle tiles (Metropolis items)
+        b->max_count = std::max(b->max_count, q.cfg.model == SMC_MODEL_CV_TRACK
+                                                  ? nt
+                                                  : ceil_div(q.cfg.n, WAVE));
         for (int64_t t = 0; t < nt; ++t) {
             (q.cfg.model == SMC_MODEL_CV_TRACK ? mpf : mgmm).push_back(make_int2(i, (int)t));
             mall.push_back(make_int2(i, (int)t));
@@ -457,6 +474,9 @@ smc_status smc_batch_step(smc_batch *b)
         return bfail(b, SMC_ERR_BAD_STATE, "smc_batch_step before smc_batch_init");
     if (b->host_step >= b->max_steps)
         return bfail(b, SMC_ERR_BAD_STATE, "no observations / schedule rows / history rows left");
+    if (b->host_step >= b->counter_steps)
+        return bfail(b, SMC_ERR_UNSUPPORTED,
+                     "step index beyond the 32-bit step counters for this batch and schedule");
     const hipError_t e = enqueue_step(b);
     if (e == hipSuccess)
         b->host_step++;
@@ -498,6 +518,9 @@ smc_status smc_batch_replay(smc_batch *b)
         return bfail(b, SMC_ERR_BAD_STATE, "smc_batch_replay before smc_batch_init");
     if (b->host_step >= b->max_steps)
         return bfail(b, SMC_ERR_BAD_STATE, "no observations / schedule rows / history rows left");
+    if (b->host_step >= b->counter_steps)
+        return bfail(b, SMC_ERR_UNSUPPORTED,
+                     "step index beyond the 32-bit step counters for this batch and schedule");
     const hipError_t e = hipGraphLaunch(b->exec, b->stream);
     if (e == hipSuccess)
         b->host_step++;
@@ -610,8 +633,10 @@ smc_status smc_batch_autotune(smc_batch *b, int32_t repeats, const char *cache_p
                     break;
                 }
                 // the first step warms up; the rest are timed one by one
+                // (within what the step counters can index)
+                const int nsteps = std::min(steps, b->counter_steps);
                 std::vector<float> ms;
-                for (int k = 0; k < steps && err == hipSuccess; ++k) {
+                for (int k = 0; k < nsteps && err == hipSuccess; ++k) {
                     err = hipEventRecord(e0, b->stream);
                     if (err == hipSuccess)
                         err = enqueue_step(b);
@@ -627,6 +652,8 @@ smc_status smc_batch_autotune(smc_batch *b, int32_t repeats, const char *cache_p
                 }
                 if (err != hipSuccess)
                     break;
+                if (ms.empty())  // no timed step fits this schedule's counters
+                    continue;
                 std::sort(ms.begin(), ms.end());
                 const float med = ms[ms.size() / 2];
                 if (med < best) {
