@@ -111,6 +111,7 @@ def load() -> ctypes.CDLL:
         "smc_move": (st, [_vp, _i32, P(smc_move_args)]),
         "smc_reweight": (st, [_vp, _i32, P(smc_reweight_args)]),
         "smc_ess": (st, [_vp, _i32, P(_d)]),
+        "smc_step": (st, [_vp, _i32, P(smc_move_args), _i32]),
         "smc_resample": (st, [_vp, _i32, _i32]),
         "smc_monitor": (st, [_vp, _i32, _vp]),
         "smc_gather": (st, [_vp]),
@@ -156,7 +157,7 @@ def load() -> ctypes.CDLL:
 def exported_symbols():
     return ["smc_status_string", "smc_state_rows", "smc_workspace_size", "smc_create",
             "smc_destroy", "smc_set_stream", "smc_init", "smc_move", "smc_reweight", "smc_ess",
-            "smc_resample", "smc_monitor", "smc_gather", "smc_copy_from", "smc_current_state",
+            "smc_resample", "smc_step", "smc_monitor", "smc_gather", "smc_copy_from", "smc_current_state",
             "smc_read_scalars", "smc_check", "smc_last_error", "smc_gmm_loglik_grad",
             "smc_draw_words", "smc_resample_weights_workspace", "smc_resample_weights",
             "smc_resample_weights_noalloc",
@@ -259,6 +260,10 @@ def smc_ess(ctx, step, host=False):
 
 def smc_resample(ctx, step, force=False):
     _check(load().smc_resample(ctx, step, int(force)), "smc_resample", ctx)
+
+
+def smc_step(ctx, step, args, force=False):
+    _check(load().smc_step(ctx, step, ctypes.byref(args), int(force)), "smc_step", ctx)
 
 
 def smc_monitor(ctx, step, out_ptr=None):

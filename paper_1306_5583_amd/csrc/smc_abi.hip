@@ -583,6 +583,46 @@ smc_status smc_resample(smc_ctx *ctx, int32_t step, int32_t force)
     return hip_status(c, e, "smc_resample");
 }
 
+smc_status smc_step(smc_ctx *ctx, int32_t step, const smc_move_args *args, int32_t force)
+{
+    if (!ctx || !args)
+        return SMC_ERR_INVALID_ARG;
+    Ctx &c = ctx->c;
+    const bool one_launch = c.cfg.model == SMC_MODEL_CV_TRACK && c.ntiles == 1 &&
+                            args->fuse_reweight != 0 && c.cfg.scheme != SMC_RS_MULTINOMIAL &&
+                            c.mon_pending_step < 0;
+    if (!one_launch) {
+        smc_status s = smc_move(ctx, step, args);
+        if (s == SMC_OK)
+            s = smc_ess(ctx, step, nullptr);
+        if (s == SMC_OK)
+            s = smc_resample(ctx, step, force);
+        return s;
+    }
+    // the checks of the three calls (the move leaves nothing pending that
+    // the normalisation or the resampling would refuse)
+    if (!c.initialised)
+        return fail(c, SMC_ERR_BAD_STATE, "smc_move before smc_init");
+    if (step < 0)
+        return fail(c, SMC_ERR_INVALID_ARG, "step must be >= 0");
+    if (args->obs_index < 0 || args->obs_index >= c.cfg.n_obs)
+        return fail(c, SMC_ERR_INVALID_ARG, "obs_index out of range");
+    const bool mon = args->monitor_step >= 0;
+    if (mon && !c.normalised)
+        return fail(c, SMC_ERR_BAD_STATE, "a fused monitor needs normalised incoming weights");
+    const hipError_t e =
+        launch_pf_step_tile(c, step, args->obs_index, c.armed_gather, c.armed_lw,
+                            mon ? args->monitor_step : -1, args->monitor_out, force);
+    if (e == hipSuccess) {
+        // as after smc_move, smc_ess and smc_resample
+        c.partials_valid = true;
+        c.normalised = true;
+        c.armed_gather = true;
+        c.armed_lw = true;
+    }
+    return hip_status(c, e, "smc_step");
+}
+
 smc_status smc_monitor(smc_ctx *ctx, int32_t step, double *out_dev)
 {
     if (!ctx)

@@ -153,6 +153,79 @@ hipError_t launch_finalize(Ctx &c, int32_t step)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// One iteration of Algorithm "pf" for a population of one tile (at most 1024
+// particles) in a single workgroup: the fused move + weight (carrying the
+// monitor of the previous step), the normalisation (Eq. si to the ESS and
+// log Z update, then the monitor's completion) and the resampling.  With one
+// workgroup nothing orders the phases but its barriers, so the step's three
+// launches become one: each phase reads what the previous one wrote.
+// ---------------------------------------------------------------------------
+template <typename T, bool MON, bool STRAT>
+__global__ __launch_bounds__(TPB) void pf_step_tile_kernel(Prob P, uint32_t t, int32_t obs_index,
+                                                           int gather_check, int reset_check,
+                                                           MonDest md, int32_t force)
+{
+    pf_move_tile<T, true, MON>(P, (const T *)P.state[0], (T *)P.state[1], 0, t,
+                               P.data + 2 * (int64_t)obs_index, gather_check != 0,
+                               reset_check != 0);
+    __syncthreads();
+    normalise_block<TPB>(P, (int32_t)t);
+    if (MON) {
+        __syncthreads();
+        monitor_block<TPB>(P, md);
+    }
+    __syncthreads();
+    if constexpr (STRAT) {
+        __shared__ double sS[TILE];
+        __shared__ double sU[RS_UCAP];
+        resample_tile<SMC_RS_STRATIFIED>(P, 0, t, force, nullptr, sS, sU);
+    } else {
+        resample_sys_tile(P, 0, t, force);
+    }
+}
+
+template <typename T, bool MON>
+static void launch_step_tile_t(Ctx &c, const Prob &P, int32_t step, int32_t obs_index,
+                               bool gather_check, bool reset_check, const MonDest &md,
+                               int32_t force)
+{
+    if (c.cfg.scheme == SMC_RS_STRATIFIED)
+        hipLaunchKernelGGL((pf_step_tile_kernel<T, MON, true>), dim3(1), dim3(TPB), 0, c.stream, P,
+                           (uint32_t)step, obs_index, (int)gather_check, (int)reset_check, md,
+                           force);
+    else
+        hipLaunchKernelGGL((pf_step_tile_kernel<T, MON, false>), dim3(1), dim3(TPB), 0, c.stream,
+                           P, (uint32_t)step, obs_index, (int)gather_check, (int)reset_check, md,
+                           force);
+}
+
+hipError_t launch_pf_step_tile(Ctx &c, int32_t step, int32_t obs_index, bool gather_check,
+                               bool reset_check, int32_t monitor_step, double *monitor_out,
+                               int32_t force)
+{
+    const Prob P = make_prob(c);
+    MonDest md = mon_dest(c, monitor_step, FIN_MON_ROWS, monitor_out);
+    const bool mon = monitor_step >= 0;
+    if (c.elem_bytes == 4) {
+        if (mon)
+            launch_step_tile_t<float, true>(c, P, step, obs_index, gather_check, reset_check, md,
+                                            force);
+        else
+            launch_step_tile_t<float, false>(c, P, step, obs_index, gather_check, reset_check, md,
+                                             force);
+    } else {
+        if (mon)
+            launch_step_tile_t<double, true>(c, P, step, obs_index, gather_check, reset_check, md,
+                                             force);
+        else
+            launch_step_tile_t<double, false>(c, P, step, obs_index, gather_check, reset_check,
+                                              md, force);
+    }
+    c.cur ^= 1;
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(TPB) void resample_sys_kernel(Prob P, uint32_t t, int32_t force)
 {
     resample_sys_tile(P, blockIdx.x, t, force);

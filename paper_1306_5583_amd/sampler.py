@@ -99,6 +99,25 @@ class _Base(ProblemBuffers):
     def check(self):
         L.smc_check(self.ctx)
 
+    def capture(self, body):
+        """Records the launches that body() enqueues on this problem into a
+        HIP graph without running them, and returns the graph; its replay()
+        runs the same launches on the current stream.  body must read nothing
+        back to the host.  The capture runs on a side stream (the default
+        stream cannot be captured); the problem's own stream is restored
+        afterwards."""
+        side = torch.cuda.Stream(self.device)
+        side.wait_stream(self.stream)
+        g = torch.cuda.CUDAGraph()
+        L.smc_set_stream(self.ctx, side.cuda_stream)
+        try:
+            with torch.cuda.graph(g, stream=side):
+                body()
+        finally:
+            L.smc_set_stream(self.ctx, self.stream.cuda_stream)
+        self.stream.wait_stream(side)
+        return g
+
 
 class ParticleFilter(_Base):
     """Bootstrap filter of the almost-constant-velocity model (Section 5.1,
@@ -132,14 +151,13 @@ class ParticleFilter(_Base):
     def step(self, t: int, monitor: bool = True):
         """One iteration: move + weight (fused, also completing the monitor
         of the previous step from the same pass), normalise, resample if
-        ESS < threshold N.  The monitor of step t is carried by the next
-        move; finish() completes the last one."""
+        ESS < threshold N (smc_step: one launch for a one-tile filter).  The
+        monitor of step t is carried by the next move; finish() completes
+        the last one."""
         m = self._margs
         m.obs_index = t
         m.monitor_step = self._mon_pending
-        L.smc_move(self.ctx, t, m)
-        L.smc_ess(self.ctx, t)
-        L.smc_resample(self.ctx, t)
+        L.smc_step(self.ctx, t, m)
         self._mon_pending = t if monitor else -1
 
     def finish(self):
@@ -148,12 +166,23 @@ class ParticleFilter(_Base):
             L.smc_monitor(self.ctx, self._mon_pending)
             self._mon_pending = -1
 
-    def run(self, monitor: bool = True) -> float:
+    def _steps(self, monitor: bool = True):
         self.init(monitor)
         for t in range(1, self.T):
             self.step(t, monitor)
         self.finish()
+
+    def run(self, monitor: bool = True) -> float:
+        self._steps(monitor)
         return self.log_z()
+
+    def capture_run(self, monitor: bool = True):
+        """The whole run (prior draws, every step, the last monitor) as one
+        HIP graph: every decision of the run is taken on the device (the
+        resampling kernels read the normalisation's flag), so one capture
+        replays the filter from its prior draws; log_z() and the history
+        read the replay's results."""
+        return self.capture(lambda: self._steps(monitor))
 
     def history_host(self) -> np.ndarray:
         torch.cuda.synchronize(self.device)
@@ -262,6 +291,10 @@ class GmmSampler(_Base):
         scales times the BlockAdapter factors (the host reads the previous
         step's acceptance counts, one synchronisation per step); the scales
         used are kept in self.scales_used[T + 1][3]."""
+        self._steps(alphas, scales, monitor, adapt)
+        return self.log_z()
+
+    def _steps(self, alphas, scales=None, monitor: bool = True, adapt: bool = False):
         self.init(monitor)
         T = len(alphas) - 1
         base = np.array([(rw_scales if self.move == "rw" else mala_scales)(
@@ -275,7 +308,15 @@ class GmmSampler(_Base):
                 acc = self.history_host()[t, L.SMC_H_ACC0:L.SMC_H_ACC0 + 3]
                 used[t + 1] = base[t + 1] * ad.update(acc, self.n)
         self.scales_used = used
-        return self.log_z()
+
+    def capture_run(self, alphas, scales=None, monitor: bool = True):
+        """The whole run at the given block scales as one HIP graph (the
+        acceptance-rate adaptation reads the acceptance counts on the host
+        between steps, so it cannot be captured): the resampling decisions
+        are taken on the device, so one capture replays the sampler from its
+        prior draws; log_z(), log_z_path() and the history read the
+        replay's results."""
+        return self.capture(lambda: self._steps(alphas, scales, monitor, False))
 
     def log_z_path(self) -> float:
         """Path-sampling estimate of log Z (Section 5.2): the trapezoid over

@@ -206,6 +206,36 @@ def test_end_to_end_small(lib, orc, move):
     s.check()
 
 
+@pytest.mark.parametrize("move", ["rw", "mala"])
+def test_captured_run_replays_match_eager(lib, move):
+    # the whole tempered run captured as one graph, replayed three times with
+    # the sampler run eagerly and the host synchronised between replays:
+    # every replay reproduces the eager run bit for bit (history with the
+    # accept counts, both log Z estimates, final state and weights)
+    pkg, L = lib
+    K, n, nd, T = 3, 3000, 90, 14
+    y = synth.gmm_data_four_components(nd, 8)
+    alphas = synth.prior_tempering(T, 4.0)
+    s = pkg.GmmSampler(n, y, K, T, seed=12, move=move)
+    logz_e = s.run(alphas)
+    ref = [s.history_host().copy(), s.state().cpu().numpy().copy(),
+           s.log_weight.cpu().numpy().copy()]
+    ps_e = s.log_z_path()
+    g = s.capture_run(alphas)
+    for r in range(3):
+        if r == 1:
+            assert s.run(alphas) == logz_e
+        _say("gmm replay", r, move)
+        g.replay()
+        torch.cuda.synchronize()
+        assert s.log_z() == logz_e
+        assert s.log_z_path() == ps_e
+        got = [s.history_host(), s.state().cpu().numpy(), s.log_weight.cpu().numpy()]
+        for u, v in zip(got, ref):
+            assert np.array_equal(u, v)
+    s.check()
+
+
 def test_alpha_zero_prior_invariance(lib):
     pkg, L = lib
     K, n, T = 4, 1 << 16, 15

@@ -204,6 +204,70 @@ def test_end_to_end_c0(lib, orc):
     pf.check()
 
 
+@pytest.mark.parametrize("n", [1, 63, 1000, 1024])
+@pytest.mark.parametrize("scheme,fp32", [("systematic", False), ("stratified", False),
+                                         ("systematic", True)])
+def test_one_launch_step_matches_three_calls(lib, n, scheme, fp32):
+    # smc_step of a one-tile filter (one launch: move + weight, normalisation
+    # with the carried monitor, resampling) against smc_move, smc_ess and
+    # smc_resample, bit for bit over a whole run; thresholds 0.5 and 1 (a
+    # resample every step)
+    pkg, L = lib
+    _, y = synth.pf_trajectory(30, 5)
+    for thr in (0.5, 1.0):
+        _say("one-launch step", n, scheme, fp32, thr)
+        a = pkg.ParticleFilter(n, y, seed=3, scheme=scheme, fp32_state=fp32, threshold=thr)
+        b = pkg.ParticleFilter(n, y, seed=3, scheme=scheme, fp32_state=fp32, threshold=thr)
+        a.run()
+        b.init()
+        mon = 0
+        for t in range(1, b.T):
+            m = b._margs
+            m.obs_index, m.monitor_step = t, mon
+            L.smc_move(b.ctx, t, m)
+            L.smc_ess(b.ctx, t)
+            L.smc_resample(b.ctx, t)
+            mon = t
+        b._mon_pending = mon
+        b.finish()
+        ha, hb = a.history_host(), b.history_host()
+        assert np.array_equal(ha, hb)
+        for u, v in [(a.state(), b.state()), (a.log_weight, b.log_weight),
+                     (a.ancestors, b.ancestors)]:
+            assert np.array_equal(u.cpu().numpy(), v.cpu().numpy())
+        assert a.log_z() == b.log_z()
+        if thr == 1.0:
+            assert np.all(ha[1:, L.SMC_H_FLAG] == 1.0)
+        a.check()
+        b.check()
+
+
+@pytest.mark.parametrize("scheme,n", [("systematic", 1000), ("multinomial", 5003)])
+def test_captured_run_replays_match_eager(lib, scheme, n):
+    # the whole run captured as one graph and replayed three times, with the
+    # filter run eagerly and the host synchronised between replays: every
+    # replay reproduces the eager run bit for bit
+    pkg, L = lib
+    _, y = synth.pf_trajectory(60, synth.DATA_SEED[0])
+    pf = pkg.ParticleFilter(n, y, seed=1, scheme=scheme)
+    logz_e = pf.run()
+    ref = [pf.history_host().copy(), pf.state().cpu().numpy().copy(),
+           pf.log_weight.cpu().numpy().copy(), pf.ancestors.cpu().numpy().copy()]
+    g = pf.capture_run()
+    for r in range(3):
+        if r == 1:
+            assert pf.run() == logz_e
+        _say("replay", r, scheme, n)
+        g.replay()
+        torch.cuda.synchronize()
+        assert pf.log_z() == logz_e
+        got = [pf.history_host(), pf.state().cpu().numpy(), pf.log_weight.cpu().numpy(),
+               pf.ancestors.cpu().numpy()]
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b)
+    pf.check()
+
+
 def test_deterministic(lib):
     pkg, L = lib
     _, y = synth.pf_trajectory(40, 3)
