@@ -583,6 +583,15 @@ smc_status smc_resample(smc_ctx *ctx, int32_t step, int32_t force)
     return hip_status(c, e, "smc_resample");
 }
 
+namespace smc {
+// Move + weight, normalisation (with the pending monitor) and resampling of
+// a one-tile tracking filter in one launch (smc_core.hip); toggles c.cur
+// like the move.
+hipError_t launch_pf_step_tile(Ctx &c, int32_t step, int32_t obs_index, bool gather_check,
+                               bool reset_check, int32_t monitor_step, double *monitor_out,
+                               int32_t force);
+}  // namespace smc
+
 smc_status smc_step(smc_ctx *ctx, int32_t step, const smc_move_args *args, int32_t force)
 {
     if (!ctx || !args)

@@ -180,11 +180,6 @@ smc_status device_ok(std::string &err);
 hipError_t launch_reset_scalars(Ctx &c);
 hipError_t launch_finalize(Ctx &c, int32_t step);
 hipError_t launch_resample(Ctx &c, int32_t step, int32_t force);
-// Move + weight, normalisation (with the pending monitor) and resampling of
-// a one-tile tracking filter in one launch; toggles c.cur like the move.
-hipError_t launch_pf_step_tile(Ctx &c, int32_t step, int32_t obs_index, bool gather_check,
-                               bool reset_check, int32_t monitor_step, double *monitor_out,
-                               int32_t force);
 hipError_t launch_monitor(Ctx &c, int32_t step, double *out_dev, int rows, bool gather_pending,
                           bool reset_pending);
 hipError_t launch_gather(Ctx &c);
