@@ -16,6 +16,13 @@ struct smc_ctx {
 
 namespace smc {
 
+// Move + weight, normalisation (with the pending monitor) and resampling of
+// a one-tile tracking filter in one launch (smc_core.hip); toggles c.cur
+// like the move.
+hipError_t launch_pf_step_tile(Ctx &c, int32_t step, int32_t obs_index, bool gather_check,
+                               bool reset_check, int32_t monitor_step, double *monitor_out,
+                               int32_t force);
+
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 static int state_rows_of(const smc_config &cfg)
@@ -582,15 +589,6 @@ smc_status smc_resample(smc_ctx *ctx, int32_t step, int32_t force)
     c.armed_gather = true;
     return hip_status(c, e, "smc_resample");
 }
-
-namespace smc {
-// Move + weight, normalisation (with the pending monitor) and resampling of
-// a one-tile tracking filter in one launch (smc_core.hip); toggles c.cur
-// like the move.
-hipError_t launch_pf_step_tile(Ctx &c, int32_t step, int32_t obs_index, bool gather_check,
-                               bool reset_check, int32_t monitor_step, double *monitor_out,
-                               int32_t force);
-}  // namespace smc
 
 smc_status smc_step(smc_ctx *ctx, int32_t step, const smc_move_args *args, int32_t force)
 {
