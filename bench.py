@@ -500,10 +500,13 @@ def bench_gmm(args):
     from paper_1306_5583_amd import GmmSampler, _lib as L
     K, n, nd, T, y, move = gmm_config(args.workload, args.move)
     alphas = synth.prior_tempering(T, 4.0)
-    # a throwaway run first (the GPU leaves its idle clock state)
+    # throwaway runs first, for at least 0.3 s (the GPU leaves its idle clock
+    # state; one short run of the small workload is not enough)
     warm = GmmSampler(n, y, K, T, seed=2, move=move)
-    warm.run(alphas[:min(T, 40) + 1])
-    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.3:
+        warm.run(alphas[:min(T, 40) + 1])
+        torch.cuda.synchronize()
     warm.close()
     s = GmmSampler(n, y, K, T, seed=1, move=move)
     blocks = 3 if K > 1 else 2

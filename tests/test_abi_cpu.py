@@ -120,6 +120,7 @@ def test_null_context_rejected(L):
     lib = L.load()
     assert lib.smc_init(None) == L.SMC_ERR_INVALID_ARG
     assert lib.smc_resample(None, 0, 0) == L.SMC_ERR_INVALID_ARG
+    assert lib.smc_step(None, 1, ctypes.byref(L.smc_move_args()), 0) == L.SMC_ERR_INVALID_ARG
     assert lib.smc_check(None) == L.SMC_ERR_INVALID_ARG
 
 
