@@ -170,11 +170,14 @@ def run_pf(args, n, fp32, scheme, steps, warmup, timing=True):
     T_needed = 1 + warmup + max(steps, PROFILE_SAMPLE)
     T = max(args.T, T_needed)
     _, y = synth.pf_trajectory(T, synth.DATA_SEED[1])
-    # a throwaway run of the same filter first: the GPU leaves its idle clock
-    # state before anything is timed (a few untimed steps are not enough)
+    # throwaway runs of the same filter first, for at least 0.3 s: the GPU
+    # leaves its idle clock state before anything is timed (a few untimed
+    # steps are not enough)
     pfw = ParticleFilter(n, y, seed=2, scheme=scheme, fp32_state=fp32)
-    pfw.run()
-    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.3:
+        pfw.run()
+        torch.cuda.synchronize()
     pfw.close()
     del pfw
 
