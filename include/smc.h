@@ -239,15 +239,17 @@ smc_status smc_ess(smc_ctx *ctx, int32_t step, double *ess_host_or_null);
  * does nothing on the device. */
 smc_status smc_resample(smc_ctx *ctx, int32_t step, int32_t force);
 
-/* One iteration of Algorithm "pf" (Section 5.1): the same as smc_move(step,
- * args), smc_ess(step, NULL) and smc_resample(step, force) in sequence, with
- * the same results bit for bit and the same errors.  For a tracking filter
- * of at most 1024 particles (one tile) with the fused weight
- * (args->fuse_reweight != 0), systematic or stratified resampling and no
- * monitor pending from an earlier move, the three are one launch of a
- * single workgroup (a small filter is bound by launch latency, not by
- * work); otherwise it makes the three calls.  The one-launch form carries
- * no timing events (smc_profile_start). */
+/* One iteration of Algorithm "pf" (Section 5.1) of a tracking filter: the
+ * same as smc_move(step, args), smc_ess(step, NULL) and smc_resample(step,
+ * force) in sequence, with the same results bit for bit and the same
+ * errors.  The move must carry the weight (args->fuse_reweight = 1; else
+ * SMC_ERR_INVALID_ARG, as for a mixture sampler's context, whose iteration
+ * takes another order).  For a filter of at most 1024 particles (one tile)
+ * with systematic or stratified resampling and no monitor pending from an
+ * earlier move, the three are one launch of a single workgroup (a small
+ * filter is bound by latency, not by work); otherwise it makes the three
+ * calls.  The one-launch form carries no timing events
+ * (smc_profile_start). */
 smc_status smc_step(smc_ctx *ctx, int32_t step, const smc_move_args *args, int32_t force);
 
 /* Importance-sampling estimate (Section 2.1 estimator 3; Section 4.1

@@ -595,8 +595,11 @@ smc_status smc_step(smc_ctx *ctx, int32_t step, const smc_move_args *args, int32
     if (!ctx || !args)
         return SMC_ERR_INVALID_ARG;
     Ctx &c = ctx->c;
-    const bool one_launch = c.cfg.model == SMC_MODEL_CV_TRACK && c.ntiles == 1 &&
-                            args->fuse_reweight != 0 && c.cfg.scheme != SMC_RS_MULTINOMIAL &&
+    if (c.cfg.model != SMC_MODEL_CV_TRACK)
+        return fail(c, SMC_ERR_INVALID_ARG, "smc_step is the tracking filter's iteration");
+    if (args->fuse_reweight == 0)
+        return fail(c, SMC_ERR_INVALID_ARG, "smc_step needs the fused weight (fuse_reweight = 1)");
+    const bool one_launch = c.ntiles == 1 && c.cfg.scheme != SMC_RS_MULTINOMIAL &&
                             c.mon_pending_step < 0;
     if (!one_launch) {
         smc_status s = smc_move(ctx, step, args);

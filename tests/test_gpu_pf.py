@@ -423,6 +423,39 @@ def test_out_of_order_calls_rejected(lib):
     assert e.value.status == L.SMC_ERR_INVALID_ARG
 
 
+@pytest.mark.parametrize("n", [100, 5000])
+def test_step_rejects_what_the_three_calls_reject(lib, n):
+    # smc_step's checks, in its one-launch form (n = 100) and as the three
+    # calls (n = 5000): before init, a bad observation row, a negative step
+    pkg, L = lib
+    _, y = synth.pf_trajectory(5, 3)
+    pf = pkg.ParticleFilter(n, y, seed=2)
+    m = L.smc_move_args()
+    m.obs_index, m.fuse_reweight = 1, 1
+    with pytest.raises(L.SmcError) as e:
+        L.smc_step(pf.ctx, 1, m)
+    assert e.value.status == L.SMC_ERR_BAD_STATE
+    pf.init()
+    m.fuse_reweight = 0  # the step's normalisation needs the move's weights
+    with pytest.raises(L.SmcError) as e:
+        L.smc_step(pf.ctx, 1, m)
+    assert e.value.status == L.SMC_ERR_INVALID_ARG
+    m.fuse_reweight = 1
+    m.obs_index = 99
+    with pytest.raises(L.SmcError) as e:
+        L.smc_step(pf.ctx, 1, m)
+    assert e.value.status == L.SMC_ERR_INVALID_ARG
+    m.obs_index = 1
+    with pytest.raises(L.SmcError) as e:
+        L.smc_step(pf.ctx, -1, m)
+    assert e.value.status == L.SMC_ERR_INVALID_ARG
+    # after the rejected calls the filter still steps and stays consistent
+    m.monitor_step = 0
+    L.smc_step(pf.ctx, 1, m)
+    L.smc_monitor(pf.ctx, 1)
+    pf.check()
+
+
 def test_move_kernel_profile_events(lib):
     # dispatch-carried timing of the move kernel: one duration per timed launch
     pkg, L = lib
