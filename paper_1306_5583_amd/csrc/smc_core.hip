@@ -155,9 +155,10 @@ hipError_t launch_finalize(Ctx &c, int32_t step)
 
 // ---------------------------------------------------------------------------
 // One iteration of Algorithm "pf" for a population of one tile (at most 1024
-// particles) in a single workgroup: the fused move + weight (carrying the
-// monitor of the previous step), the normalisation (Eq. si to the ESS and
-// log Z update, then the monitor's completion) and the resampling.  With one
+// particles) in a single workgroup: the fused move + weight (Eq. si,
+// carrying the monitor of the previous step), the normalisation (Section 2.1
+// ESS, Section 2.2 log Z update, then the monitor's completion) and the
+// resampling (Section 2.1, Eq. resample).  With one
 // workgroup nothing orders the phases but its barriers, so the step's three
 // launches become one: each phase reads what the previous one wrote.
 // ---------------------------------------------------------------------------
